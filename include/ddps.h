@@ -1,0 +1,224 @@
+/*
+ * ddps.h -- C ABI of the MI355X (gfx950) DDPS solver.
+ *
+ * DDPS (Manguoglu, "A domain-decomposing parallel sparse linear system
+ * solver", arXiv 1008.1700) solves Ax = f for a row-partitioned sparse A:
+ * Section 3, Figure 1, stages 1-5 form the preconditioner P = D~ + R~ without
+ * a right-hand side (ddps_setup + ddps_factor), and stage 6 runs a Krylov
+ * method with P applied as in Figure 2 (ddps_solve).
+ *
+ * Conventions for every entry point:
+ *   - Return value: a ddps_status (0 = DDPS_OK, negative = error).  No C++
+ *     exception ever crosses the ABI.
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example a torch tensor's data_ptr()); "host" pointers are ordinary CPU
+ *     memory.  Every pointer argument below says which it is.
+ *   - All GPU work is ordered on the stream given in ddps_options.stream
+ *     (0 = the null stream).  Calls that return ddps_info synchronise that
+ *     stream before returning.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ *
+ * Matrix requirements of the GPU path (checked by ddps_setup, DDPS_E_ARG if
+ * violated): A is square, CSR with int64 row pointers and int32 column
+ * indices (sorted or not), finite values; the half-bandwidth
+ * b = max |i - j| over stored entries satisfies b >= 1, and, with
+ * t = b rounded up to a multiple of 64, every block has at least 2t rows
+ * when p > 1.  Then each block A_ii is block tridiagonal in t x t tiles and
+ * R_i couples block i only with the last t rows of block i-1 and the first
+ * t rows of block i+1.
+ */
+#ifndef DDPS_H
+#define DDPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddps_ctx* ddps_handle;
+
+typedef enum {
+  DDPS_OK = 0,
+  DDPS_E_ARG = -1,        /* invalid argument or unsupported matrix structure */
+  DDPS_E_NOMEM = -2,      /* the plan does not fit the memory budget (the paper's failure F1) */
+  DDPS_E_NOCONV = -3,     /* tolerance not met after outer_maxit (the paper's failure F2) */
+  DDPS_E_SINGULAR = -4,   /* a pivot of a diagonal-block LU is (numerically) zero */
+  DDPS_E_BREAKDOWN = -5,  /* BiCGStab broke down twice (after one restart) */
+  DDPS_E_STATE = -6,      /* call out of order (e.g. solve before factor) */
+  DDPS_E_HIP = -7         /* a HIP runtime call failed */
+} ddps_status;
+
+/* Arithmetic of the block factors and spikes (stages 2 and 4). */
+typedef enum {
+  DDPS_F64 = 0,     /* FP64 storage, FP64 MFMA */
+  DDPS_F32 = 1,     /* FP32 storage, FP32 MFMA */
+  DDPS_BF16X3 = 2,  /* FP32 storage; products on bf16 MFMA with each FP32 operand split
+                       into two bf16 terms (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+  DDPS_BF16 = 3     /* FP32 storage; products on bf16 MFMA with one bf16 term per operand */
+} ddps_dtype;
+
+typedef struct {
+  int32_t struct_size;     /* sizeof(ddps_options), for forward compatibility */
+  double drop_delta;       /* delta of the column-dropping rule (Section 3), in [0,1]; 0 keeps
+                              every nonzero coupling column */
+  int32_t factor_dtype;    /* ddps_dtype */
+  double inner_tol;        /* BiCGStab on the reduced system: stop at ||g^ - G^ z^||_2 / ||g^||_2
+                              <= inner_tol (Figure 2, step 6.3) */
+  int32_t inner_maxit;     /* maximum inner iterations */
+  int32_t outer_maxit;     /* maximum outer iterations (Section 4 uses 1000) */
+  int32_t outer_method;    /* 0 = preconditioned BiCGStab (Section 4), 1 = iterative refinement
+                              x += P^{-1}(f - Ax) */
+  int32_t guess;           /* 0: reduced solve starts at z^ = 0; 1: from the vector given to
+                              ddps_set_guess (kept until replaced) */
+  int32_t use_x0;          /* 1: x is read as the initial outer iterate */
+  int32_t max_rhs;         /* largest k passed to ddps_solve_many (>= 1) */
+  size_t mem_budget;       /* bytes the handle may allocate; 0 = free device memory */
+  void* stream;            /* hipStream_t on which all work is ordered */
+} ddps_options;
+
+typedef struct {
+  double outer_iters;       /* outer iterations in half steps, as counted in the paper's
+                               iteration tables (0.5 = converged after the first half step) */
+  double inner_iters_avg;   /* average BiCGStab iterations per reduced solve */
+  int64_t inner_iters_total;
+  int32_t applications;     /* preconditioner applications (Figure 2 solves) */
+  double relres_inf;        /* ||f - Ax||_inf / ||f||_inf of the returned x (worst column) */
+  double relres_2;          /* ||f - Ax||_2 / ||f||_2 of the returned x (worst column) */
+  double t_setup_ms, t_factor_ms, t_solve_ms;   /* device time of the last call of each */
+  int32_t bad_block;        /* DDPS_E_SINGULAR: block of the first bad pivot, else -1 */
+  int64_t bad_row;          /* DDPS_E_SINGULAR: global row of that pivot, else -1 */
+} ddps_info;
+
+/* Fills *opt with the defaults: delta 0, FP64 factors, inner_tol 1e-12,
+ * inner_maxit 1000, outer_maxit 1000, iterative refinement, zero guess,
+ * max_rhs 1, no memory budget, null stream. */
+void ddps_default_options(ddps_options* opt);
+
+/* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row
+ * partition part_ptr, apply the dropping rule to the columns of each R_i and
+ * build the index set c of kept coupling columns.
+ *   n, p:        matrix order and number of blocks (p >= 1).
+ *   part_ptr:    host, int64[p+1]; block i owns rows [part_ptr[i], part_ptr[i+1]);
+ *                part_ptr[0] = 0, strictly increasing, part_ptr[p] = n.
+ *   row_ptr:     device, int64[n+1]; col: device, int32[nnz]; val: device, double[nnz].
+ *   opt:         host, may be NULL for the defaults.
+ * The library copies what it needs: the caller may free the CSR arrays when
+ * the call returns.  On success *h owns all device memory of the solver.
+ * Errors: DDPS_E_ARG (bad partition, indices out of range, non-finite values,
+ * unsupported structure), DDPS_E_NOMEM (plan larger than the budget: nothing
+ * is left allocated), DDPS_E_HIP. */
+int ddps_setup(ddps_handle* h, int64_t n, int32_t p, const int64_t* part_ptr,
+               const int64_t* row_ptr, const int32_t* col, const double* val, int64_t nnz,
+               const ddps_options* opt);
+
+/* Stages 2 and 4 (Figure 1): LU of every diagonal block A_ii, without
+ * pivoting, and the spikes G_i = A_ii^{-1} R~_i(:, c_i) for all blocks, in
+ * the factor dtype.  The reduced matrix G^ = I(c,c) + G(c,c) of Figure 2,
+ * step 6.2, is the set of spike rows at c; it is used in place.
+ * Errors: DDPS_E_SINGULAR (info of the next ddps_solve reports the block and
+ * row; also readable with ddps_last_singular), DDPS_E_HIP. */
+int ddps_factor(ddps_handle h);
+
+/* Replaces the values of A (same sparsity pattern as at setup; device,
+ * double[nnz]) and redoes stages 1, 3 and 5; call ddps_factor next. */
+int ddps_refactor_values(ddps_handle h, const double* val);
+
+/* Stage 6 (Figure 1) with P z = y solved as in Figure 2: solves Ax = f to
+ * ||f - Ax||_inf / ||f||_inf <= tol.
+ *   f: device, double[n], read only.  x: device, double[n], written (read
+ *   first if use_x0).  info: host, may be NULL.
+ * Errors: DDPS_E_STATE (not factored), DDPS_E_NOCONV (the paper's F2; x
+ * holds the last iterate), DDPS_E_BREAKDOWN, DDPS_E_HIP. */
+int ddps_solve(ddps_handle h, const double* f, double* x, double tol, ddps_info* info);
+
+/* As ddps_solve for k right-hand sides at once (columns of F, X, column-major
+ * with leading dimensions ldf, ldx >= n; device).  Each column runs its own
+ * Krylov scalars; the block sweeps, reduced-matrix products and retrievals
+ * are shared passes over the factors and spikes.  1 <= k <= max_rhs. */
+int ddps_solve_many(ddps_handle h, int32_t k, const double* F, int64_t ldf, double* X, int64_t ldx,
+                    double tol, ddps_info* info);
+
+/* Sets the initial guess of the reduced solve (used when opt.guess = 1):
+ * device, double[m * k] laid out like ddps_reduced_layout's c, one column of
+ * m entries per right-hand side.  The vector is copied. */
+int ddps_set_guess(ddps_handle h, const double* zhat0, int32_t k);
+
+/* Reduced-system layout.  *m receives the number of candidate coupling
+ * columns m = 2 t (p - 1) (host).  If c is not NULL it receives (device,
+ * int64[m]) the global column index of each candidate, ascending; if mask is
+ * not NULL it receives (device, double[m]) 1 for candidates in the index set
+ * c of stage 5 and 0 for dropped or structurally zero columns.  t and b
+ * (host, may be NULL) receive the tile size and half-bandwidth. */
+int ddps_reduced_layout(ddps_handle h, int64_t* m, int64_t* c, double* mask, int32_t* t, int32_t* b);
+
+/* Reduced vectors of the last preconditioner application of the last solve
+ * (for recording training pairs of the learned guess): g^ (Figure 2, 6.2)
+ * and z^ (6.3), device double[m * k] each; either may be NULL. */
+int ddps_last_reduced(ddps_handle h, double* ghat, double* zhat);
+
+/* One application of P^{-1} (Figure 2, steps 6.1-6.5): z = P^{-1} y for k
+ * columns (device, column-major, leading dimension n).  If ghat/zhat are not
+ * NULL they receive g^ and z^ (device, double[m*k]).  The inner solve uses
+ * opt.inner_tol and the current guess setting.  inner_iters (host, may be
+ * NULL) receives the iterations of each column's reduced solve. */
+int ddps_apply_preconditioner(ddps_handle h, int32_t k, const double* y, double* z, double* ghat,
+                              double* zhat, double* inner_iters);
+
+/* Step 6.1 only: g = D~^{-1} y (device, double[n*k]). */
+int ddps_block_solve(ddps_handle h, int32_t k, const double* y, double* g);
+
+/* The reduced operator of step 6.2: v = G^ x restricted to the index set c
+ * (entries outside c act as the identity); device double[m*k]. */
+int ddps_reduced_matvec(ddps_handle h, int32_t k, const double* x, double* v);
+
+/* Copies of the factored blocks, as double, for checking.  Block `blk`
+ * (0-based) has T = ceil(n_i / t) tile rows and is padded at the top with
+ * pad = T t - n_i identity rows.
+ *   which = 0: the diagonal tile k holding inverse factors: strictly below
+ *              the diagonal L_kk^{-1} (unit diagonal implied), on and above
+ *              it U_kk^{-1};
+ *   which = 1: L_{k+1,k}, the sub-diagonal tile of L (k < T-1);
+ *   which = 2: U_{k,k+1}, the super-diagonal tile of U (k < T-1).
+ * dst: device, double[t*t], column-major. */
+int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* dst);
+
+/* Spikes of block blk as double: dst (device, double[n_i * 2t], column-major,
+ * leading dimension n_i, padding rows removed); columns [0,t) multiply the
+ * last t columns of block blk-1, columns [t,2t) the first t columns of block
+ * blk+1 (all zero where that neighbour does not exist). */
+int ddps_get_spikes(ddps_handle h, int32_t blk, double* dst);
+
+/* Tile size t and per-block padded sizes: tiles (host, int32[p]) receives
+ * T_i and pads (host, int32[p]) the padding of each block; either may be NULL. */
+int ddps_block_shape(ddps_handle h, int32_t* t, int32_t* tiles, int32_t* pads);
+
+/* Block and global row of the first bad pivot found by the last ddps_factor
+ * (host pointers; -1 if none). */
+int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
+
+/* Per-kernel timing for roofline reporting.  ddps_timing_enable(h, kind, 1)
+ * records HIP events around every launch of that kernel kind on the handle's
+ * stream; ddps_timing_read reports launches, summed device milliseconds and
+ * the algorithmic flops and bytes of those launches (host pointers), then
+ * clears the counters.  kind: 0 = grouped GEMM (factor and spikes),
+ * 1 = diagonal-tile LU, 2 = block-sweep GEMV, 3 = reduced-matrix product,
+ * 4 = retrieval, 5 = CSR SpMV. */
+int ddps_timing_enable(ddps_handle h, int32_t kind, int32_t on);
+int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms, double* flops,
+                     double* bytes);
+
+/* Device bytes held by the handle (host pointer). */
+int ddps_memory(ddps_handle h, size_t* bytes);
+
+/* Releases every resource of the handle; NULL is ignored. */
+void ddps_destroy(ddps_handle h);
+
+/* Static string for a status code. */
+const char* ddps_status_string(int s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDPS_H */

@@ -1,0 +1,1432 @@
+// Host runtime and C ABI of the DDPS solver (see include/ddps.h).
+//
+// Layout.  With b the half-bandwidth of A and t = b rounded up to 64, every
+// block A_ii is block tridiagonal in t x t tiles (block rows shorter than a
+// multiple of t are padded on top with identity rows).  ddps_factor performs
+// an unpivoted LU of each block in this tile form:
+//     for k = 0..T-1:  S_k = A_kk - L_{k,k-1} U_{k-1,k}        (Schur update)
+//                      S_k = L_kk U_kk, stored as L_kk^{-1}, U_kk^{-1}
+//                      L_{k+1,k} = A_{k+1,k} U_kk^{-1},  U_{k,k+1} = L_kk^{-1} A_{k,k+1}
+// and the spikes G_i = A_ii^{-1} R_i(:, c_i) by a forward sweep (only the
+// columns coupling to block i-1 need one: the others are supported on the
+// last tile) and a backward sweep over all 2t columns.  Keeping the inverse
+// triangles of the diagonal tiles turns every step of both sweeps into a
+// GEMM (factor phase, MFMA) or a GEMV (solve phase, HBM stream).
+//
+// Execution.  Every phase is a static schedule of grouped launches built once
+// per handle: a launch carries one problem descriptor per block, so all
+// blocks advance together and one launch fills the GPU.
+#include "../../include/ddps.h"
+#include "ddps_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ddps;
+
+namespace {
+
+enum LaunchKind { LK_GEMM = 0, LK_PANEL = 1, LK_GEMV = 2 };
+enum TimingKind { TK_GEMM = 0, TK_PANEL = 1, TK_SWEEP = 2, TK_RSPMV = 3, TK_RETR = 4, TK_CSR = 5, TK_N = 6 };
+
+struct Launch {
+  int kind;
+  int64_t off;
+  int nprob;
+  int nwg;
+  double flops;
+  double bytes;
+};
+
+struct TimingRec {
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct Status {
+  int code;
+};
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) {                        \
+      last_hip_error() = e_;                       \
+      return DDPS_E_HIP;                           \
+    }                                              \
+  } while (0)
+
+hipError_t& last_hip_error() {
+  static thread_local hipError_t e = hipSuccess;
+  return e;
+}
+
+}  // namespace
+
+struct ddps_ctx {
+  ddps_options opt{};
+  hipStream_t stream = nullptr;
+  int64_t n = 0, nnz = 0;
+  int p = 0;
+  std::vector<int64_t> part;
+  int32_t b = 0, t = 0;
+  int sdt = 0;   // storage dtype of factors/spikes: 0 f64, 1 f32
+  int gdt = 0;   // GEMM arithmetic: 0 f64, 1 f32, 2 bf16x3, 3 bf16
+  size_t elt = 8;
+  std::vector<BlockInfo> blk;
+  int Tmax = 0;
+  int64_t Np = 0, m = 0, ntiles = 0, nspike = 0, scr_per_block = 0;
+  int R = 1;
+  // device data
+  int64_t *d_part = nullptr, *d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val = nullptr;
+  BlockInfo* d_blk = nullptr;
+  void *d_tiles = nullptr, *d_spikes = nullptr, *d_scratch = nullptr;
+  unsigned long long *d_colnorm = nullptr, *d_blknorm = nullptr, *d_bad = nullptr, *d_band = nullptr;
+  unsigned int* d_flags = nullptr;
+  double* d_thresh = nullptr;
+  double* d_mask = nullptr;
+  int64_t *d_c = nullptr, *d_rrow = nullptr;
+  GemmProb* d_gemm = nullptr;
+  PanelProb* d_panel = nullptr;
+  GemvProb* d_gemv = nullptr;
+  double *d_ypad = nullptr, *d_vpad = nullptr;
+  double *d_gh = nullptr, *d_zh = nullptr, *d_r = nullptr, *d_rt = nullptr, *d_p = nullptr,
+         *d_v = nullptr, *d_s = nullptr, *d_tv = nullptr, *d_guess = nullptr;
+  double *d_part_buf = nullptr, *d_sums = nullptr, *d_out = nullptr;
+  KState* d_state = nullptr;
+  int32_t* d_flag = nullptr;
+  double *d_fo = nullptr, *d_xo = nullptr, *d_ro = nullptr, *d_z = nullptr, *d_rto = nullptr,
+         *d_po = nullptr, *d_vo = nullptr, *d_ph = nullptr, *d_sh = nullptr, *d_to = nullptr;
+  int64_t part_cap = 0;
+  // host staging (pinned)
+  KState* h_state = nullptr;
+  double* h_out = nullptr;
+  // schedules
+  std::vector<Launch> sch_factor, sch_fwd, sch_bwd, sch_retr;
+  Launch l_pv{}, l_st{}, l_zv{};  // reduced products: p->v (dot r~), s->t (dots), z->v
+  int W1 = 0;
+  bool factored = false;
+  int guess_k = 0;
+  // last solve
+  int last_k = 0;
+  // timing
+  bool tim_on[TK_N] = {};
+  std::vector<TimingRec> tim[TK_N];
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_setup_ms = 0, t_factor_ms = 0, t_solve_ms = 0;
+  int32_t bad_block = -1;
+  int64_t bad_row = -1;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  template <typename T>
+  int alloc(T*& ptr, int64_t count) {
+    ptr = nullptr;
+    if (count <= 0) return DDPS_OK;
+    void* q = nullptr;
+    const size_t sz = (size_t)count * sizeof(T);
+    if (hipMalloc(&q, sz) != hipSuccess) return DDPS_E_NOMEM;
+    allocs.push_back(q);
+    bytes += sz;
+    ptr = (T*)q;
+    return DDPS_OK;
+  }
+  int alloc_raw(void*& ptr, size_t sz) {
+    ptr = nullptr;
+    if (sz == 0) return DDPS_OK;
+    if (hipMalloc(&ptr, sz) != hipSuccess) return DDPS_E_NOMEM;
+    allocs.push_back(ptr);
+    bytes += sz;
+    return DDPS_OK;
+  }
+
+  // ---- addressing -------------------------------------------------------
+  char* tile(int i, int which, int k) const {  // which: 0 diag, 1 L_{k+1,k}, 2 U_{k,k+1}
+    const BlockInfo& B = blk[i];
+    const int64_t idx = B.tiles + (which == 0 ? k : which == 1 ? B.T + k : 2 * B.T - 1 + k);
+    return (char*)d_tiles + (size_t)idx * t * t * elt;
+  }
+  char* sub(char* tile_base, int r, int c) const {  // element (r, c) of a t x t tile
+    return tile_base + ((size_t)c * t + r) * elt;
+  }
+  char* spike(int i, int64_t row, int64_t col) const {
+    const BlockInfo& B = blk[i];
+    return (char*)d_spikes + (size_t)(B.goff + col * B.N + row) * elt;
+  }
+  // scratch of block i: [WY | WA1 | WA2 | WB | WL (64 x t, ld 64) | WU (t x 64, ld t)]
+  char* scr(int i, int which) const {
+    const int64_t tt = (int64_t)t * t;
+    int64_t off = 0;
+    switch (which) {
+      case 0: off = 0; break;
+      case 1: off = tt; break;
+      case 2: off = 2 * tt; break;
+      case 3: off = 3 * tt; break;
+      case 4: off = 4 * tt; break;
+      default: off = 4 * tt + 64 * (int64_t)t; break;
+    }
+    return (char*)d_scratch + (size_t)(i * scr_per_block + off) * elt;
+  }
+
+  void tim_begin(int kind, hipEvent_t& a) {
+    a = nullptr;
+    if (!tim_on[kind]) return;
+    a = get_event();
+    hipEventRecord(a, stream);
+  }
+  void tim_end(int kind, hipEvent_t a, double flops, double bytes_) {
+    if (!a) return;
+    hipEvent_t b2 = get_event();
+    hipEventRecord(b2, stream);
+    tim[kind].push_back({a, b2, flops, bytes_});
+  }
+  hipEvent_t get_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+};
+
+namespace {
+
+double gemm_prob_flops(const GemmProb& P) {
+  double f = 0.0;
+  for (int I0 = 0; I0 < P.M; I0 += 64)
+    for (int J0 = 0; J0 < P.N; J0 += 64) {
+      int kb = 0, ke = P.K;
+      if (P.flags & G_A_UP) kb = std::max(kb, I0);
+      if (P.flags & G_B_LO) kb = std::max(kb, J0);
+      if (P.flags & G_A_LO) ke = std::min(ke, I0 + 64);
+      if (P.flags & G_B_UP) ke = std::min(ke, J0 + 64);
+      if (ke > kb) f += 2.0 * 64 * 64 * (ke - kb);
+    }
+  return f;
+}
+
+struct ScheduleBuilder {
+  ddps_ctx* h;
+  std::vector<GemmProb> gemm;
+  std::vector<PanelProb> panel;
+  std::vector<GemvProb> gemv;
+  // current launch
+  int kind = -1;
+  int64_t off = 0;
+  int nwg = 0;
+  double flops = 0, bytes = 0;
+
+  void begin(int k) {
+    kind = k;
+    nwg = 0;
+    flops = bytes = 0;
+    off = k == LK_GEMM ? (int64_t)gemm.size() : k == LK_PANEL ? (int64_t)panel.size() : (int64_t)gemv.size();
+  }
+  void end(std::vector<Launch>& out) {
+    const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
+                                                                              : (int64_t)gemv.size()) - off;
+    if (cnt > 0 && nwg > 0) out.push_back({kind, off, (int)cnt, nwg, flops, bytes});
+  }
+  Launch end_one() {
+    const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
+    return Launch{kind, off, (int)cnt, nwg, flops, bytes};
+  }
+  void add_gemm(const void* A, int lda, const void* B, int ldb, const void* C0, int ldc0, void* D, int ldd,
+                int M, int N, int K, int flags) {
+    if (M <= 0 || N <= 0) return;
+    GemmProb P{};
+    P.A = A; P.B = B; P.C0 = C0; P.D = D;
+    P.M = M; P.N = N; P.K = K;
+    P.lda = lda; P.ldb = ldb; P.ldc0 = ldc0; P.ldd = ldd;
+    P.flags = flags | (C0 ? G_C0 : 0);
+    P.tile0 = nwg;
+    nwg += (M / 64) * (N / 64);
+    flops += gemm_prob_flops(P);
+    gemm.push_back(P);
+  }
+  void add_copy(const void* src, int lds, void* dst, int ldd, int M, int N) {
+    add_gemm(nullptr, 0, nullptr, 0, src, lds, dst, ldd, M, N, 0, 0);
+  }
+  void add_panel(void* D, int ld, int block, int64_t row0) {
+    PanelProb P{};
+    P.D = D; P.ld = ld; P.block = block; P.row0 = row0;
+    panel.push_back(P);
+    nwg += 1;
+    flops += 2.0 / 3.0 * 64 * 64 * 64 * 2.0;
+  }
+  void add_gemv(const GemvProb& G0, double elt_bytes) {
+    GemvProb G = G0;
+    if (G.rows <= 0) return;
+    G.wg0 = nwg;
+    nwg += G.rows / 64;
+    double cols = std::max(0, G.ce - G.cb);
+    double frac = G.tri ? 0.5 : 1.0;
+    flops += 2.0 * G.rows * cols * frac;
+    bytes += (double)G.rows * cols * frac * elt_bytes + 8.0 * G.rows * 2;
+    gemv.push_back(G);
+  }
+};
+
+int fac_dtype_code(int d) {
+  switch (d) {
+    case DDPS_F64: return 0;
+    case DDPS_F32: return 1;
+    case DDPS_BF16X3: return 2;
+    case DDPS_BF16: return 3;
+    default: return -1;
+  }
+}
+
+void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb) {
+  const int t = h->t, p = h->p, Q = t / 64;
+  auto& S = h->sch_factor;
+  for (int k = 0; k < h->Tmax; ++k) {
+    std::vector<int> act;
+    for (int i = 0; i < p; ++i)
+      if (h->blk[i].T > k) act.push_back(i);
+    // pre(k): Schur update, top-spike right-hand side, staging copies
+    sb.begin(LK_GEMM);
+    for (int i : act) {
+      const BlockInfo& B = h->blk[i];
+      const int N = (int)B.N;
+      if (k >= 1)
+        sb.add_gemm(h->tile(i, 1, k - 1), t, h->tile(i, 2, k - 1), t, h->tile(i, 0, k), t, h->tile(i, 0, k), t,
+                    t, t, t, G_NEG | G_A_UP | G_B_LO);
+      if (i > 0) {
+        if (k >= 1)
+          sb.add_gemm(h->tile(i, 1, k - 1), t, h->spike(i, (int64_t)(k - 1) * t, 0), N,
+                      h->spike(i, (int64_t)k * t, 0), N, h->scr(i, 0), t, t, t, t, G_NEG | G_A_UP);
+        else
+          sb.add_copy(h->spike(i, 0, 0), N, h->scr(i, 0), t, t, t);
+      }
+      if (k < B.T - 1) {
+        sb.add_copy(h->tile(i, 1, k), t, h->scr(i, 1), t, t, t);
+        sb.add_copy(h->tile(i, 2, k), t, h->scr(i, 2), t, t, t);
+      }
+      if (k == B.T - 1 && i < p - 1) sb.add_copy(h->spike(i, (int64_t)k * t, t), N, h->scr(i, 3), t, t, t);
+    }
+    sb.end(S);
+    // LU of S_k with inverse triangles, 64-column panels
+    for (int j = 0; j < Q; ++j) {
+      const int j64 = j * 64, rest = t - (j + 1) * 64;
+      sb.begin(LK_PANEL);
+      for (int i : act) {
+        const BlockInfo& B = h->blk[i];
+        sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64);
+      }
+      sb.end(S);
+      sb.begin(LK_GEMM);
+      for (int i : act) {
+        char* D = h->tile(i, 0, k);
+        if (rest > 0) {
+          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
+                      rest, 64, 64, G_B_MUP | G_B_UP);
+          sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
+                      64, rest, 64, G_A_MLU | G_A_LO);
+        }
+        if (j > 0) {
+          sb.add_gemm(h->sub(D, j64, 0), t, D, t, nullptr, 0, h->scr(i, 4), 64, 64, j64, j64, G_B_MLU | G_B_LO);
+          sb.add_gemm(D, t, h->sub(D, 0, j64), t, nullptr, 0, h->scr(i, 5), t, j64, 64, j64, G_A_MUP | G_A_UP);
+        }
+      }
+      sb.end(S);
+      sb.begin(LK_GEMM);
+      for (int i : act) {
+        char* D = h->tile(i, 0, k);
+        if (rest > 0)
+          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
+                      h->sub(D, j64 + 64, j64 + 64), t, rest, rest, 64, G_NEG);
+        if (j > 0) {
+          sb.add_gemm(h->sub(D, j64, j64), t, h->scr(i, 4), 64, nullptr, 0, h->sub(D, j64, 0), t, 64, j64, 64,
+                      G_NEG | G_A_MLU | G_A_LO);
+          sb.add_gemm(h->scr(i, 5), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, 0, j64), t, j64, 64, 64,
+                      G_NEG | G_B_MUP | G_B_UP);
+        }
+      }
+      sb.end(S);
+    }
+    // post(k): off-diagonal factors and forward spike sweep
+    sb.begin(LK_GEMM);
+    for (int i : act) {
+      const BlockInfo& B = h->blk[i];
+      const int N = (int)B.N;
+      char* D = h->tile(i, 0, k);
+      if (k < B.T - 1) {
+        sb.add_gemm(h->scr(i, 1), t, D, t, nullptr, 0, h->tile(i, 1, k), t, t, t, t, G_A_UP | G_B_MUP | G_B_UP);
+        sb.add_gemm(D, t, h->scr(i, 2), t, nullptr, 0, h->tile(i, 2, k), t, t, t, t, G_A_MLU | G_A_LO | G_B_LO);
+      }
+      if (i > 0) sb.add_gemm(D, t, h->scr(i, 0), t, nullptr, 0, h->spike(i, (int64_t)k * t, 0), N, t, t, t, G_A_MLU | G_A_LO);
+      if (k == B.T - 1 && i < p - 1)
+        sb.add_gemm(D, t, h->scr(i, 3), t, nullptr, 0, h->spike(i, (int64_t)k * t, t), N, t, t, t,
+                    G_A_MLU | G_A_LO | G_B_LO);
+    }
+    sb.end(S);
+  }
+  // backward spike sweep over all spike columns
+  if (p > 1) {
+    for (int s = 0; s < h->Tmax; ++s) {
+      std::vector<int> act;
+      for (int i = 0; i < p; ++i)
+        if (h->blk[i].T > s) act.push_back(i);
+      sb.begin(LK_GEMM);
+      for (int i : act) {
+        const BlockInfo& B = h->blk[i];
+        const int N = (int)B.N, k = (int)B.T - 1 - s;
+        const int c0 = i == 0 ? t : 0, c1 = i == p - 1 ? t : 2 * t;
+        char* W = h->scr(i, 0) + (size_t)c0 * t * h->elt;
+        if (k < B.T - 1)
+          sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N, h->spike(i, (int64_t)k * t, c0), N,
+                      W, t, t, c1 - c0, t, G_NEG | G_A_LO);
+        else
+          sb.add_copy(h->spike(i, (int64_t)k * t, c0), N, W, t, t, c1 - c0);
+      }
+      sb.end(S);
+      sb.begin(LK_GEMM);
+      for (int i : act) {
+        const BlockInfo& B = h->blk[i];
+        const int N = (int)B.N, k = (int)B.T - 1 - s;
+        const int c0 = i == 0 ? t : 0, c1 = i == p - 1 ? t : 2 * t;
+        char* W = h->scr(i, 0) + (size_t)c0 * t * h->elt;
+        sb.add_gemm(h->tile(i, 0, k), t, W, t, nullptr, 0, h->spike(i, (int64_t)k * t, c0), N, t, c1 - c0, t,
+                    G_A_MUP | G_A_UP);
+      }
+      sb.end(S);
+    }
+  }
+}
+
+void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
+  const int t = h->t, p = h->p;
+  const double eb = (double)h->elt;
+  double* yp = h->d_ypad;
+  double* vp = h->d_vpad;
+  for (int k = 0; k < h->Tmax; ++k) {
+    sb.begin(LK_GEMV);
+    for (int i = 0; i < p; ++i) {
+      const BlockInfo& B = h->blk[i];
+      if (B.T <= k) continue;
+      GemvProb G{};
+      G.A = k >= 1 ? h->tile(i, 1, k - 1) : h->tile(i, 0, k);
+      G.lda = t;
+      G.x1 = yp + B.voff + (int64_t)(k >= 1 ? k - 1 : 0) * t;
+      G.x2 = G.x1;
+      G.split = t;
+      G.rows = t;
+      G.cb = 0;
+      G.ce = k >= 1 ? t : 0;
+      G.yin = yp + B.voff + (int64_t)k * t;
+      G.yout = vp + B.voff + (int64_t)k * t;
+      G.flags = V_NEG | V_YIN;
+      G.tri = 2;
+      sb.add_gemv(G, eb);
+    }
+    sb.end(h->sch_fwd);
+    sb.begin(LK_GEMV);
+    for (int i = 0; i < p; ++i) {
+      const BlockInfo& B = h->blk[i];
+      if (B.T <= k) continue;
+      GemvProb G{};
+      G.A = h->tile(i, 0, k);
+      G.lda = t;
+      G.x1 = vp + B.voff + (int64_t)k * t;
+      G.x2 = G.x1;
+      G.split = t;
+      G.rows = t;
+      G.cb = 0;
+      G.ce = t;
+      G.yout = yp + B.voff + (int64_t)k * t;
+      G.flags = V_A_MLU;
+      G.tri = 1;
+      sb.add_gemv(G, eb);
+    }
+    sb.end(h->sch_fwd);
+  }
+  for (int s = 0; s < h->Tmax; ++s) {
+    sb.begin(LK_GEMV);
+    for (int i = 0; i < p; ++i) {
+      const BlockInfo& B = h->blk[i];
+      if (B.T <= s) continue;
+      const int k = (int)B.T - 1 - s;
+      GemvProb G{};
+      G.A = k < B.T - 1 ? h->tile(i, 2, k) : h->tile(i, 0, k);
+      G.lda = t;
+      G.x1 = yp + B.voff + (int64_t)(k < B.T - 1 ? k + 1 : k) * t;
+      G.x2 = G.x1;
+      G.split = t;
+      G.rows = t;
+      G.cb = 0;
+      G.ce = k < B.T - 1 ? t : 0;
+      G.yin = yp + B.voff + (int64_t)k * t;
+      G.yout = vp + B.voff + (int64_t)k * t;
+      G.flags = V_NEG | V_YIN;
+      G.tri = 1;
+      sb.add_gemv(G, eb);
+    }
+    sb.end(h->sch_bwd);
+    sb.begin(LK_GEMV);
+    for (int i = 0; i < p; ++i) {
+      const BlockInfo& B = h->blk[i];
+      if (B.T <= s) continue;
+      const int k = (int)B.T - 1 - s;
+      GemvProb G{};
+      G.A = h->tile(i, 0, k);
+      G.lda = t;
+      G.x1 = vp + B.voff + (int64_t)k * t;
+      G.x2 = G.x1;
+      G.split = t;
+      G.rows = t;
+      G.cb = 0;
+      G.ce = t;
+      G.yout = yp + B.voff + (int64_t)k * t;
+      G.flags = V_A_MUP;
+      G.tri = 2;
+      sb.add_gemv(G, eb);
+    }
+    sb.end(h->sch_bwd);
+  }
+  // retrieval z = g - G z^ into vpad
+  sb.begin(LK_GEMV);
+  for (int i = 0; i < p; ++i) {
+    const BlockInfo& B = h->blk[i];
+    GemvProb G{};
+    G.A = h->spike(i, 0, 0);
+    G.lda = B.N;
+    G.x1 = h->d_zh + (i > 0 ? (int64_t)2 * (i - 1) * t : 0);
+    G.x2 = h->d_zh + (i < p - 1 ? (int64_t)(2 * i + 1) * t : 0);
+    G.split = t;
+    G.rows = (int)B.N;
+    G.cb = (i == 0 || p == 1) ? t : 0;
+    G.ce = (i == p - 1) ? t : 2 * t;
+    if (p == 1) G.cb = G.ce = 0;
+    G.yin = yp + B.voff;
+    G.yout = vp + B.voff;
+    G.flags = V_NEG | V_YIN;
+    G.tri = 0;
+    sb.add_gemv(G, eb);
+  }
+  sb.end(h->sch_retr);
+  // reduced products
+  auto reduced = [&](const double* X, double* Y, const double* dotv, int dflags) {
+    sb.begin(LK_GEMV);
+    for (int i = 0; i < p && p > 1; ++i) {
+      const BlockInfo& B = h->blk[i];
+      for (int part = 0; part < 2; ++part) {
+        if (part == 0 && i == 0) continue;
+        if (part == 1 && i == p - 1) continue;
+        const int64_t ro = part == 0 ? (int64_t)(2 * i - 1) * t : (int64_t)2 * i * t;
+        GemvProb G{};
+        G.A = h->spike(i, part == 0 ? B.pad : B.N - t, 0);
+        G.lda = B.N;
+        G.x1 = X + (i > 0 ? (int64_t)2 * (i - 1) * t : 0);
+        G.x2 = X + (i < p - 1 ? (int64_t)(2 * i + 1) * t : 0);
+        G.split = t;
+        G.rows = t;
+        G.cb = i == 0 ? t : 0;
+        G.ce = i == p - 1 ? t : 2 * t;
+        G.yin = X + ro;
+        G.yout = Y + ro;
+        G.mask = h->d_mask + ro;
+        G.dot_off = ro;
+        G.flags = V_YIN | V_MASK | dflags;
+        G.tri = 0;
+        sb.add_gemv(G, eb);
+      }
+    }
+    (void)dotv;
+    return sb.end_one();
+  };
+  h->l_pv = reduced(h->d_p, h->d_v, h->d_rt, V_DOT);
+  h->l_st = reduced(h->d_s, h->d_tv, h->d_s, V_DOT | V_DOT2);
+  h->l_zv = reduced(h->d_zh, h->d_v, nullptr, 0);
+  h->W1 = h->l_pv.nwg;
+}
+
+int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, const double* dotv,
+               double* partial, const int32_t* stop, int tkind) {
+  hipEvent_t a;
+  h->tim_begin(tkind, a);
+  switch (L.kind) {
+    case LK_GEMM: launch_gemm(h->gdt, 0, h->d_gemm + L.off, L.nprob, L.nwg, h->stream); break;
+    case LK_PANEL:
+      launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, h->stream);
+      break;
+    default:
+      launch_gemv(h->sdt, R, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, h->stream);
+      break;
+  }
+  h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV ? R : 1), L.bytes);
+  return DDPS_OK;
+}
+
+int rhs_alloc(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; }
+
+// ---------------------------------------------------------------- phases
+int do_scatter(ddps_ctx* h) {
+  hipStream_t s = h->stream;
+  const int64_t tcount = h->ntiles * (int64_t)h->t * h->t;
+  if (h->sdt == 0) {
+    fill_f64((double*)h->d_tiles, tcount, 0.0, s);
+    fill_f64((double*)h->d_spikes, h->nspike, 0.0, s);
+  } else {
+    fill_f32((float*)h->d_tiles, tcount, 0.f, s);
+    fill_f32((float*)h->d_spikes, h->nspike, 0.f, s);
+  }
+  fill_u64(h->d_colnorm, (int64_t)h->p * 2 * h->t, 0ull, s);
+  fill_u64(h->d_bad, 1, ~0ull, s);
+  fill_f64(h->d_mask, h->m, 0.0, s);
+  setup_scatter(h->sdt, h->n, h->p, h->t, h->d_part, h->d_blk, h->d_rowptr, h->d_col, h->d_val, h->d_tiles,
+                h->d_spikes, h->d_colnorm, h->d_flags, s);
+  setup_mask(h->sdt, h->p, h->t, h->opt.drop_delta, h->d_blk, h->d_colnorm, h->d_mask, h->d_spikes, s);
+  return DDPS_OK;
+}
+
+int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, int64_t ldy, int tk_gemv) {
+  for (const Launch& L : S) {
+    const int tk = L.kind == LK_GEMM ? TK_GEMM : L.kind == LK_PANEL ? TK_PANEL : tk_gemv;
+    run_launch(h, L, R, ldx, ldy, nullptr, nullptr, nullptr, tk);
+  }
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
+// Inner BiCGStab on G^ z^ = g^ for R columns (k used).  z^ in d_zh.
+int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::vector<int>& iters,
+                std::vector<int>& status_out) {
+  const int R = h->R;
+  const int64_t m = h->m;
+  hipStream_t s = h->stream;
+  iters.assign(k, 0);
+  status_out.assign(k, KS_CONVERGED);
+  if (m == 0) {
+    return DDPS_OK;
+  }
+  const int W2 = vec_grid(m);
+  double* S0 = h->d_sums;
+  double* S1 = S0 + 2 * kMaxRhs;
+  double* S2 = S1 + 2 * kMaxRhs;
+  double* S3 = S2 + 2 * kMaxRhs;
+  double* S4 = S3 + 2 * kMaxRhs;
+  if (use_guess) {
+    HIPCHK(hipMemcpyAsync(h->d_zh, h->d_guess, sizeof(double) * m * R, hipMemcpyDeviceToDevice, s));
+    run_launch(h, h->l_zv, R, m, m, nullptr, nullptr, nullptr, TK_RSPMV);
+  }
+  bicg_init(R, m, use_guess, h->d_gh, h->d_zh, h->d_v, h->d_r, h->d_rt, h->d_p, h->d_part_buf, W2, s);
+  reduce2(R, W2, h->d_part_buf, S0, nullptr, s);
+  bicg_init_state(R, k, tol, S0, h->d_state, s);
+  std::vector<int> restarts(k, 0);
+  int it = 1;
+  const int batch = 4;
+  bool done = false;
+  std::vector<int32_t> flags(kMaxRhs, 0);
+  while (!done) {
+    int last = std::min(maxit, it + batch - 1);
+    for (; it <= last; ++it) {
+      const int32_t* stop = &h->d_state->status[it & 1][0];
+      run_launch(h, h->l_pv, R, m, m, h->d_rt, h->d_part_buf, stop, TK_RSPMV);
+      reduce2(R, h->W1, h->d_part_buf, S1, stop, s);
+      bicg_s(R, it, m, S1, h->d_state, h->d_r, h->d_v, h->d_s, h->d_part_buf, W2, s);
+      reduce2(R, W2, h->d_part_buf, S2, stop, s);
+      run_launch(h, h->l_st, R, m, m, h->d_s, h->d_part_buf, stop, TK_RSPMV);
+      reduce2(R, h->W1, h->d_part_buf, S3, stop, s);
+      bicg_xr(R, it, m, tol, S1, S2, S3, h->d_state, h->d_zh, h->d_p, h->d_s, h->d_tv, h->d_r, h->d_rt,
+              h->d_part_buf, W2, s);
+      reduce2(R, W2, h->d_part_buf, S4, stop, s);
+      bicg_p(R, it, maxit, m, tol, S1, S2, S3, S4, h->d_state, h->d_r, h->d_p, h->d_v, W2, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // status of the next iteration (slot `it & 1`, it already advanced)
+    const int32_t* stt = h->h_state->status[it & 1];
+    bool any_running = false, any_restart = false;
+    std::fill(flags.begin(), flags.end(), 0);
+    for (int j = 0; j < k; ++j) {
+      if (stt[j] == KS_RUNNING) any_running = true;
+      if (stt[j] == KS_BREAKDOWN && restarts[j] == 0 && it <= maxit) {
+        flags[j] = 1;
+        restarts[j] = 1;
+        any_restart = true;
+      }
+    }
+    if (any_restart) {
+      HIPCHK(hipMemcpyAsync(h->d_flag, flags.data(), sizeof(int32_t) * kMaxRhs, hipMemcpyHostToDevice, s));
+      bicg_restart(R, it - 1, m, h->d_flag, h->d_r, h->d_rt, h->d_p, h->d_part_buf, W2, S0, h->d_state, s);
+      any_running = true;
+    }
+    if (!any_running || it > maxit) done = true;
+  }
+  HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(KState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    iters[j] = h->h_state->iters2[j];
+    status_out[j] = h->h_state->status[it & 1][j];
+  }
+  return DDPS_OK;
+}
+
+// z = P^{-1} y (k columns, device, leading dims ldy/ldz).  Reduced vectors
+// are left in d_gh / d_zh.
+int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int64_t ldz, double inner_tol,
+               int use_guess, std::vector<int>& iters, int* breakdown) {
+  const int R = h->R;
+  hipStream_t s = h->stream;
+  vec_to_padded(h->Np, R, h->p, h->d_blk, y, ldy, h->d_ypad, s);
+  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_gh, s);
+  std::vector<int> st;
+  rc = inner_solve(h, k, use_guess, inner_tol, h->opt.inner_maxit, iters, st);
+  if (rc) return rc;
+  if (breakdown) {
+    *breakdown = 0;
+    for (int j = 0; j < k; ++j)
+      if (st[j] == KS_BREAKDOWN) *breakdown = 1;
+  }
+  rc = run_schedule(h, h->sch_retr, R, h->m, h->Np, TK_RETR);
+  if (rc) return rc;
+  vec_from_padded(h->Np, R, h->p, h->d_blk, h->d_vpad, z, ldz, s);
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
+int resid(ddps_ctx* h, const double* x, double* r, std::vector<double>& rinf, std::vector<double>& r2,
+          std::vector<double>& finf, std::vector<double>& f2) {
+  const int R = h->R;
+  const int W = vec_grid(h->n);
+  hipEvent_t a;
+  h->tim_begin(TK_CSR, a);
+  csr_resid(R, h->n, h->d_rowptr, h->d_col, h->d_val, x, h->n, h->d_fo, h->n, r, h->n, h->d_part_buf, W,
+            h->d_out, h->stream);
+  h->tim_end(TK_CSR, a, 2.0 * h->nnz * R, 12.0 * h->nnz + 8.0 * h->n * (R * 3 + 2));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  rinf.resize(R); r2.resize(R); finf.resize(R); f2.resize(R);
+  for (int j = 0; j < R; ++j) {
+    rinf[j] = h->h_out[4 * j];
+    r2[j] = std::sqrt(h->h_out[4 * j + 1]);
+    finf[j] = h->h_out[4 * j + 2];
+    f2[j] = std::sqrt(h->h_out[4 * j + 3]);
+  }
+  return DDPS_OK;
+}
+
+// out = A x
+int matvec(ddps_ctx* h, const double* x, double* out) {
+  const int R = h->R;
+  const int W = vec_grid(h->n);
+  hipEvent_t a;
+  h->tim_begin(TK_CSR, a);
+  csr_resid(R, h->n, h->d_rowptr, h->d_col, h->d_val, x, h->n, nullptr, h->n, out, h->n, h->d_part_buf, W,
+            h->d_out, h->stream);
+  h->tim_end(TK_CSR, a, 2.0 * h->nnz * R, 12.0 * h->nnz + 8.0 * h->n * (R * 2 + 1));
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
+int dots(ddps_ctx* h, int64_t len, const double* a0, const double* b0, const double* a1, const double* b1,
+         std::vector<double>& d0, std::vector<double>& d1) {
+  const int R = h->R;
+  const int W = vec_grid(len);
+  dot2(R, len, a0, b0, a1, b1, h->d_part_buf, W, h->d_out, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  d0.resize(R); d1.resize(R);
+  for (int j = 0; j < R; ++j) {
+    d0[j] = h->h_out[2 * j];
+    d1[j] = h->h_out[2 * j + 1];
+  }
+  return DDPS_OK;
+}
+
+// max |v| per column (host)
+int norm_inf(ddps_ctx* h, const double* v, std::vector<double>& out) {
+  const int R = h->R;
+  const int W = vec_grid(h->n);
+  csr_resid(R, h->n, nullptr, nullptr, nullptr, nullptr, h->n, v, h->n, nullptr, h->n, h->d_part_buf, W,
+            h->d_out, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out.resize(R);
+  for (int j = 0; j < R; ++j) out[j] = h->h_out[4 * j];
+  return DDPS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+void ddps_default_options(ddps_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(ddps_options);
+  o->drop_delta = 0.0;
+  o->factor_dtype = DDPS_F64;
+  o->inner_tol = 1e-12;
+  o->inner_maxit = 1000;
+  o->outer_maxit = 1000;
+  o->outer_method = 1;
+  o->guess = 0;
+  o->use_x0 = 0;
+  o->max_rhs = 1;
+  o->mem_budget = 0;
+  o->stream = nullptr;
+}
+
+const char* ddps_status_string(int s) {
+  switch (s) {
+    case DDPS_OK: return "DDPS_OK";
+    case DDPS_E_ARG: return "DDPS_E_ARG: invalid argument or unsupported matrix structure";
+    case DDPS_E_NOMEM: return "DDPS_E_NOMEM: the plan does not fit the memory budget (F1)";
+    case DDPS_E_NOCONV: return "DDPS_E_NOCONV: tolerance not met (F2)";
+    case DDPS_E_SINGULAR: return "DDPS_E_SINGULAR: zero pivot in a diagonal-block LU";
+    case DDPS_E_BREAKDOWN: return "DDPS_E_BREAKDOWN: BiCGStab breakdown";
+    case DDPS_E_STATE: return "DDPS_E_STATE: call out of order";
+    case DDPS_E_HIP: return "DDPS_E_HIP: HIP runtime error";
+    default: return "unknown ddps status";
+  }
+}
+
+void ddps_destroy(ddps_handle h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  for (int k = 0; k < TK_N; ++k)
+    for (auto& r : h->tim[k]) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+  for (auto e : h->ev_pool) hipEventDestroy(e);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  for (void* q : h->allocs) hipFree(q);
+  if (h->h_state) hipHostFree(h->h_state);
+  if (h->h_out) hipHostFree(h->h_out);
+  delete h;
+}
+
+int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, const int64_t* row_ptr,
+               const int32_t* col, const double* val, int64_t nnz, const ddps_options* opt) {
+  if (!out) return DDPS_E_ARG;
+  *out = nullptr;
+  if (n <= 0 || p <= 0 || !part_ptr || !row_ptr || !col || !val || nnz <= 0) return DDPS_E_ARG;
+  if (nnz > (int64_t)std::numeric_limits<int64_t>::max() / 16) return DDPS_E_ARG;
+  if (part_ptr[0] != 0 || part_ptr[p] != n) return DDPS_E_ARG;
+  for (int i = 0; i < p; ++i)
+    if (part_ptr[i + 1] <= part_ptr[i]) return DDPS_E_ARG;
+  ddps_ctx* h = new (std::nothrow) ddps_ctx();
+  if (!h) return DDPS_E_NOMEM;
+  ddps_default_options(&h->opt);
+  if (opt) {
+    if (opt->struct_size != (int32_t)sizeof(ddps_options)) {
+      delete h;
+      return DDPS_E_ARG;
+    }
+    h->opt = *opt;
+  }
+  const ddps_options& o = h->opt;
+  if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
+      o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0)) {
+    delete h;
+    return DDPS_E_ARG;
+  }
+  auto fail = [&](int rc) {
+    ddps_destroy(h);
+    return rc;
+  };
+  h->stream = (hipStream_t)o.stream;
+  h->n = n;
+  h->nnz = nnz;
+  h->p = p;
+  h->part.assign(part_ptr, part_ptr + p + 1);
+  h->gdt = fac_dtype_code(o.factor_dtype);
+  h->sdt = h->gdt == 0 ? 0 : 1;
+  h->elt = h->sdt == 0 ? 8 : 4;
+  h->R = rhs_alloc(o.max_rhs);
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) return fail(DDPS_E_HIP);
+  if (hipHostMalloc((void**)&h->h_state, sizeof(KState)) != hipSuccess) return fail(DDPS_E_HIP);
+  if (hipHostMalloc((void**)&h->h_out, sizeof(double) * 4 * kMaxRhs) != hipSuccess) return fail(DDPS_E_HIP);
+  hipEventRecord(h->ev0, h->stream);
+
+  // copy the CSR and scan it
+  int rc;
+  if ((rc = h->alloc(h->d_part, p + 1)) || (rc = h->alloc(h->d_rowptr, n + 1)) || (rc = h->alloc(h->d_col, nnz)) ||
+      (rc = h->alloc(h->d_val, nnz)) || (rc = h->alloc(h->d_band, 1)) || (rc = h->alloc(h->d_flags, 1)) ||
+      (rc = h->alloc(h->d_blknorm, p)) || (rc = h->alloc(h->d_thresh, p)) || (rc = h->alloc(h->d_bad, 1)))
+    return fail(rc);
+  hipStream_t s = h->stream;
+  if (hipMemcpyAsync(h->d_part, part_ptr, sizeof(int64_t) * (p + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_rowptr, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_col, col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_val, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(DDPS_E_HIP);
+  fill_u64(h->d_band, 1, 0ull, s);
+  fill_u64(h->d_blknorm, p, 0ull, s);
+  {
+    unsigned int* f = h->d_flags;
+    fill_f32((float*)f, 1, 0.f, s);
+  }
+  setup_scan(n, p, h->d_part, h->d_rowptr, h->d_col, h->d_val, nnz, h->d_band, h->d_flags, h->d_blknorm, s);
+  unsigned long long band = 0;
+  unsigned int flags = 0;
+  if (hipMemcpyAsync(&band, h->d_band, sizeof(band), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(DDPS_E_HIP);
+  if (flags) return fail(DDPS_E_ARG);
+  h->b = (int32_t)std::max<unsigned long long>(band, 1ull);
+  h->t = ((h->b + 63) / 64) * 64;
+  const int t = h->t;
+  // layout
+  h->blk.resize(p);
+  int64_t tiles = 0, goff = 0, voff = 0;
+  h->Tmax = 0;
+  for (int i = 0; i < p; ++i) {
+    BlockInfo& B = h->blk[i];
+    B.s = part_ptr[i];
+    B.n = part_ptr[i + 1] - part_ptr[i];
+    if (p > 1 && B.n < 2 * (int64_t)t) return fail(DDPS_E_ARG);
+    B.T = (B.n + t - 1) / t;
+    B.N = B.T * t;
+    B.pad = B.N - B.n;
+    if (B.N > std::numeric_limits<int32_t>::max()) return fail(DDPS_E_ARG);
+    B.tiles = tiles;
+    tiles += 3 * B.T - 2;
+    B.goff = goff;
+    goff += p > 1 ? B.N * 2 * t : 0;
+    B.voff = voff;
+    voff += B.N;
+    h->Tmax = std::max<int>(h->Tmax, (int)B.T);
+  }
+  h->ntiles = tiles;
+  h->nspike = goff;
+  h->Np = voff;
+  h->m = p > 1 ? (int64_t)2 * t * (p - 1) : 0;
+  h->scr_per_block = 4 * (int64_t)t * t + 128 * (int64_t)t;
+  // memory plan (F1 check before the large allocations)
+  const int R = h->R;
+  const int64_t m = h->m;
+  const int64_t Wmax = std::max<int64_t>({(int64_t)kVecGrid, (int64_t)p * 2 * t / 64 + 1, 1});
+  size_t need = 0;
+  need += (size_t)h->ntiles * t * t * h->elt;
+  need += (size_t)h->nspike * h->elt;
+  need += (size_t)p * h->scr_per_block * h->elt;
+  need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
+  need += (size_t)h->Np * R * 8 * 2;
+  need += (size_t)m * R * 8 * 9;
+  need += (size_t)n * R * 8 * 10;
+  need += (size_t)Wmax * R * 4 * 8;
+  size_t budget = o.mem_budget;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(DDPS_E_HIP);
+    budget = fr > ((size_t)1 << 30) ? fr - ((size_t)1 << 30) : fr;
+  }
+  if (need > budget) return fail(DDPS_E_NOMEM);
+  void* vp;
+  if ((rc = h->alloc_raw(vp, (size_t)h->ntiles * t * t * h->elt))) return fail(rc);
+  h->d_tiles = vp;
+  if ((rc = h->alloc_raw(vp, (size_t)std::max<int64_t>(h->nspike, 1) * h->elt))) return fail(rc);
+  h->d_spikes = vp;
+  if ((rc = h->alloc_raw(vp, (size_t)p * h->scr_per_block * h->elt))) return fail(rc);
+  h->d_scratch = vp;
+  if ((rc = h->alloc(h->d_colnorm, (int64_t)p * 2 * t)) || (rc = h->alloc(h->d_mask, std::max<int64_t>(m, 1))) ||
+      (rc = h->alloc(h->d_c, std::max<int64_t>(m, 1))) || (rc = h->alloc(h->d_rrow, std::max<int64_t>(m, 1))) ||
+      (rc = h->alloc(h->d_blk, p)) || (rc = h->alloc(h->d_ypad, h->Np * R)) || (rc = h->alloc(h->d_vpad, h->Np * R)))
+    return fail(rc);
+  const int64_t mR = std::max<int64_t>(m, 1) * R;
+  if ((rc = h->alloc(h->d_gh, mR)) || (rc = h->alloc(h->d_zh, mR)) || (rc = h->alloc(h->d_r, mR)) ||
+      (rc = h->alloc(h->d_rt, mR)) || (rc = h->alloc(h->d_p, mR)) || (rc = h->alloc(h->d_v, mR)) ||
+      (rc = h->alloc(h->d_s, mR)) || (rc = h->alloc(h->d_tv, mR)) || (rc = h->alloc(h->d_guess, mR)))
+    return fail(rc);
+  const int64_t nR = n * R;
+  if ((rc = h->alloc(h->d_fo, nR)) || (rc = h->alloc(h->d_xo, nR)) || (rc = h->alloc(h->d_ro, nR)) ||
+      (rc = h->alloc(h->d_z, nR)) || (rc = h->alloc(h->d_rto, nR)) || (rc = h->alloc(h->d_po, nR)) ||
+      (rc = h->alloc(h->d_vo, nR)) || (rc = h->alloc(h->d_ph, nR)) || (rc = h->alloc(h->d_sh, nR)) ||
+      (rc = h->alloc(h->d_to, nR)))
+    return fail(rc);
+  h->part_cap = Wmax * R * 4;
+  if ((rc = h->alloc(h->d_part_buf, h->part_cap)) || (rc = h->alloc(h->d_sums, 5 * 2 * kMaxRhs)) ||
+      (rc = h->alloc(h->d_out, 4 * kMaxRhs)) || (rc = h->alloc(h->d_state, 1)) || (rc = h->alloc(h->d_flag, kMaxRhs)))
+    return fail(rc);
+  // zero every vector buffer once (unused RHS columns stay finite)
+  for (double* q : {h->d_ypad, h->d_vpad}) fill_f64(q, h->Np * R, 0.0, s);
+  for (double* q : {h->d_gh, h->d_zh, h->d_r, h->d_rt, h->d_p, h->d_v, h->d_s, h->d_tv, h->d_guess})
+    fill_f64(q, mR, 0.0, s);
+  for (double* q : {h->d_fo, h->d_xo, h->d_ro, h->d_z, h->d_rto, h->d_po, h->d_vo, h->d_ph, h->d_sh, h->d_to})
+    fill_f64(q, nR, 0.0, s);
+  // reduced-space index maps
+  if (m > 0) {
+    std::vector<int64_t> c(m), rrow(m);
+    for (int j = 0; j < p - 1; ++j) {
+      const BlockInfo& A = h->blk[j];
+      const BlockInfo& B = h->blk[j + 1];
+      for (int q = 0; q < 2 * t; ++q) {
+        const int64_t idx = (int64_t)2 * j * t + q;
+        c[idx] = B.s - t + q;
+        rrow[idx] = q < t ? A.voff + A.N - t + q : B.voff + B.pad + (q - t);
+      }
+    }
+    if (hipMemcpyAsync(h->d_c, c.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->d_rrow, rrow.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(DDPS_E_HIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(DDPS_E_HIP);
+  }
+  if (hipMemcpyAsync(h->d_blk, h->blk.data(), sizeof(BlockInfo) * p, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(DDPS_E_HIP);
+  const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
+  setup_thresh(p, eps, h->d_blknorm, h->d_thresh, s);
+  // schedules
+  ScheduleBuilder sb;
+  sb.h = h;
+  build_factor_schedule(h, sb);
+  build_solve_schedules(h, sb);
+  if ((rc = h->alloc(h->d_gemm, (int64_t)sb.gemm.size())) || (rc = h->alloc(h->d_panel, (int64_t)sb.panel.size())) ||
+      (rc = h->alloc(h->d_gemv, (int64_t)sb.gemv.size())))
+    return fail(rc);
+  if ((!sb.gemm.empty() && hipMemcpyAsync(h->d_gemm, sb.gemm.data(), sizeof(GemmProb) * sb.gemm.size(),
+                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!sb.panel.empty() && hipMemcpyAsync(h->d_panel, sb.panel.data(), sizeof(PanelProb) * sb.panel.size(),
+                                           hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!sb.gemv.empty() && hipMemcpyAsync(h->d_gemv, sb.gemv.data(), sizeof(GemvProb) * sb.gemv.size(),
+                                          hipMemcpyHostToDevice, s) != hipSuccess))
+    return fail(DDPS_E_HIP);
+  if ((int64_t)h->W1 * R * 2 > h->part_cap) return fail(DDPS_E_ARG);
+  hipEventRecord(h->ev1, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(DDPS_E_HIP);
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  h->t_setup_ms = ms;
+  *out = h;
+  return DDPS_OK;
+}
+
+int ddps_factor(ddps_handle h) {
+  if (!h) return DDPS_E_ARG;
+  hipEventRecord(h->ev0, h->stream);
+  int rc = do_scatter(h);
+  if (rc) return rc;
+  rc = run_schedule(h, h->sch_factor, 1, 0, 0, TK_GEMM);
+  if (rc) return rc;
+  hipEventRecord(h->ev1, h->stream);
+  unsigned long long bad = 0;
+  unsigned int flags = 0;
+  HIPCHK(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  h->t_factor_ms = ms;
+  if (flags) return DDPS_E_ARG;
+  if (bad != ~0ull) {
+    h->bad_block = (int32_t)(bad >> 40);
+    h->bad_row = (int64_t)(bad & ((1ull << 40) - 1));
+    h->factored = false;
+    return DDPS_E_SINGULAR;
+  }
+  h->bad_block = -1;
+  h->bad_row = -1;
+  h->factored = true;
+  return DDPS_OK;
+}
+
+int ddps_refactor_values(ddps_handle h, const double* val) {
+  if (!h || !val) return DDPS_E_ARG;
+  HIPCHK(hipMemcpyAsync(h->d_val, val, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+  fill_u64(h->d_band, 1, 0ull, h->stream);
+  fill_u64(h->d_blknorm, h->p, 0ull, h->stream);
+  fill_f32((float*)h->d_flags, 1, 0.f, h->stream);
+  setup_scan(h->n, h->p, h->d_part, h->d_rowptr, h->d_col, h->d_val, h->nnz, h->d_band, h->d_flags, h->d_blknorm,
+             h->stream);
+  const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
+  setup_thresh(h->p, eps, h->d_blknorm, h->d_thresh, h->stream);
+  unsigned int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->factored = false;
+  return flags ? DDPS_E_ARG : DDPS_OK;
+}
+
+static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double* X, int64_t ldx, double tol,
+                      ddps_info* info) {
+  if (!h || !F || !X || k < 1 || k > h->opt.max_rhs || ldf < h->n || ldx < h->n || !(tol > 0.0)) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  hipStream_t s = h->stream;
+  const int R = h->R;
+  const int64_t n = h->n;
+  hipEventRecord(h->ev0, s);
+  // internal copies with leading dimension n; unused columns are zero
+  HIPCHK(hipMemcpy2DAsync(h->d_fo, n * 8, F, ldf * 8, n * 8, k, hipMemcpyDeviceToDevice, s));
+  if (h->opt.use_x0)
+    HIPCHK(hipMemcpy2DAsync(h->d_xo, n * 8, X, ldx * 8, n * 8, k, hipMemcpyDeviceToDevice, s));
+  else
+    fill_f64(h->d_xo, n * R, 0.0, s);
+  const bool guess = h->opt.guess == 1 && h->guess_k > 0;
+  std::vector<double> rinf, r2, finf, f2;
+  int rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2);
+  if (rc) return rc;
+  std::vector<double> fnorm(finf.begin(), finf.end()), f2n(f2.begin(), f2.end());
+  auto conv_col = [&](int j, double ri) { return ri <= tol * fnorm[j] || fnorm[j] == 0.0; };
+  double outer = 0;
+  int64_t inner_total = 0;
+  int apps = 0;
+  bool breakdown = false;
+  std::vector<int> its;
+  int bk = 0;
+  auto all_conv = [&](const std::vector<double>& ri) {
+    for (int j = 0; j < k; ++j)
+      if (!conv_col(j, ri[j])) return false;
+    return true;
+  };
+  auto papply = [&](const double* y, double* z) -> int {
+    // the guess seeds the reduced solve of the first application only; later
+    // applications act on residuals, for which it is no approximation
+    int r = prec_apply(h, k, y, n, z, n, h->opt.inner_tol, (guess && apps == 0) ? 1 : 0, its, &bk);
+    if (r) return r;
+    ++apps;
+    for (int j = 0; j < k; ++j) inner_total += its[j];
+    if (bk) breakdown = true;
+    return DDPS_OK;
+  };
+  if (h->opt.outer_method == 1) {
+    // iterative refinement: x += P^{-1} (f - A x)
+    while (!all_conv(rinf) && outer < h->opt.outer_maxit) {
+      if ((rc = papply(h->d_ro, h->d_z))) return rc;
+      // columns already converged keep their x
+      Coef3 cf{};
+      for (int j = 0; j < R; ++j) {
+        cf.a[j] = 1.0;
+        cf.b[j] = (j < k && !conv_col(j, rinf[j])) ? 1.0 : 0.0;
+      }
+      lincomb(R, n, cf, h->d_xo, h->d_z, nullptr, h->d_xo, s);
+      if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
+      outer += 1;
+    }
+  } else {
+    // preconditioned BiCGStab (Templates form), convergence tested after
+    // each half step on the inf-norm relative residual; per-column scalars
+    std::vector<double> rho(R, 1.0), rho_old(R, 1.0), alpha(R, 0.0), omega(R, 1.0), d0, d1, nrm;
+    std::vector<int> active(R, 0);
+    for (int j = 0; j < k; ++j) active[j] = conv_col(j, rinf[j]) ? 0 : 1;
+    HIPCHK(hipMemcpyAsync(h->d_rto, h->d_ro, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
+    int restarts = 0;
+    bool fresh = true;
+    Coef3 cf{};
+    for (int it = 1; it <= h->opt.outer_maxit; ++it) {
+      bool any = false;
+      for (int j = 0; j < k; ++j) any |= active[j] != 0;
+      if (!any) break;
+      if ((rc = dots(h, n, h->d_rto, h->d_ro, nullptr, nullptr, d0, d1))) return rc;
+      bool brk = false;
+      for (int j = 0; j < R; ++j) {
+        rho[j] = d0[j];
+        if (j < k && active[j] && rho[j] == 0.0) brk = true;
+      }
+      for (int j = 0; j < R; ++j) {
+        const double beta = (!fresh && active[j]) ? (rho[j] / rho_old[j]) * (alpha[j] / omega[j]) : 0.0;
+        cf.a[j] = 1.0; cf.b[j] = beta; cf.c[j] = -beta * omega[j];
+      }
+      lincomb(R, n, cf, h->d_ro, h->d_po, h->d_vo, h->d_po, s);
+      fresh = false;
+      if ((rc = papply(h->d_po, h->d_ph))) return rc;
+      if ((rc = matvec(h, h->d_ph, h->d_vo))) return rc;
+      if ((rc = dots(h, n, h->d_rto, h->d_vo, nullptr, nullptr, d0, d1))) return rc;
+      for (int j = 0; j < R; ++j) {
+        alpha[j] = 0.0;
+        if (j >= k || !active[j]) continue;
+        if (d0[j] == 0.0 || !std::isfinite(rho[j] / d0[j])) brk = true;
+        else alpha[j] = rho[j] / d0[j];
+      }
+      // s = r - alpha v (d_sh); a column whose ||s|| meets the tolerance takes
+      // x += alpha p^ and stops after this half step
+      for (int j = 0; j < R; ++j) { cf.a[j] = 1.0; cf.b[j] = -alpha[j]; cf.c[j] = 0.0; }
+      lincomb(R, n, cf, h->d_ro, h->d_vo, nullptr, h->d_sh, s);
+      if ((rc = norm_inf(h, h->d_sh, nrm))) return rc;
+      std::vector<int> half(R, 0);
+      bool anyh = false, anyfull = false;
+      for (int j = 0; j < k; ++j)
+        if (active[j] && alpha[j] != 0.0 && conv_col(j, nrm[j])) { half[j] = 1; anyh = true; }
+      if (anyh) {
+        for (int j = 0; j < R; ++j) { cf.a[j] = 1.0; cf.b[j] = half[j] ? alpha[j] : 0.0; cf.c[j] = 0.0; }
+        lincomb(R, n, cf, h->d_xo, h->d_ph, nullptr, h->d_xo, s);
+      }
+      for (int j = 0; j < k; ++j) {
+        if (half[j]) { active[j] = 0; outer = std::max(outer, it - 0.5); }
+        anyfull |= active[j] != 0;
+      }
+      if (!anyfull) break;
+      if ((rc = papply(h->d_sh, h->d_z))) return rc;   // s^ in d_z
+      if ((rc = matvec(h, h->d_z, h->d_to))) return rc;
+      if ((rc = dots(h, n, h->d_to, h->d_sh, h->d_to, h->d_to, d0, d1))) return rc;
+      for (int j = 0; j < R; ++j) omega[j] = (j < k && active[j] && d1[j] != 0.0) ? d0[j] / d1[j] : 0.0;
+      // x += alpha p^ + omega s^ ;  r = s - omega t   (inactive columns unchanged)
+      for (int j = 0; j < R; ++j) {
+        const bool a = j < k && active[j];
+        cf.a[j] = 1.0; cf.b[j] = a ? alpha[j] : 0.0; cf.c[j] = a ? omega[j] : 0.0;
+      }
+      lincomb(R, n, cf, h->d_xo, h->d_ph, h->d_z, h->d_xo, s);
+      for (int j = 0; j < R; ++j) {
+        const bool a = j < k && active[j];
+        cf.a[j] = a ? 1.0 : 0.0; cf.b[j] = a ? -omega[j] : 0.0; cf.c[j] = a ? 0.0 : 1.0;
+      }
+      lincomb(R, n, cf, h->d_sh, h->d_to, h->d_ro, h->d_ro, s);
+      if ((rc = norm_inf(h, h->d_ro, nrm))) return rc;
+      for (int j = 0; j < k; ++j) {
+        if (!active[j]) continue;
+        outer = std::max(outer, (double)it);
+        if (conv_col(j, nrm[j])) active[j] = 0;
+        else if (omega[j] == 0.0) brk = true;
+      }
+      rho_old = rho;
+      if (brk) {
+        if (restarts >= 1) { breakdown = true; break; }
+        ++restarts;
+        HIPCHK(hipMemcpyAsync(h->d_rto, h->d_ro, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
+        fresh = true;
+      }
+    }
+  }
+  // true residual of the final iterate
+  if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
+  HIPCHK(hipMemcpy2DAsync(X, ldx * 8, h->d_xo, n * 8, n * 8, k, hipMemcpyDeviceToDevice, s));
+  hipEventRecord(h->ev1, s);
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  h->t_solve_ms = ms;
+  h->last_k = k;
+  double worst_inf = 0, worst_2 = 0;
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    const double ri = fnorm[j] > 0 ? rinf[j] / fnorm[j] : 0.0;
+    const double rt = f2n[j] > 0 ? r2[j] / f2n[j] : 0.0;
+    worst_inf = std::max(worst_inf, ri);
+    worst_2 = std::max(worst_2, rt);
+    if (!(ri <= tol)) ok = false;
+  }
+  if (h->opt.outer_method == 1 && outer == 0 && ok) outer = 0;
+  if (info) {
+    info->outer_iters = outer;
+    info->inner_iters_total = inner_total / 2;
+    info->applications = apps;
+    info->inner_iters_avg = apps ? (double)inner_total / 2.0 / ((double)apps * k) : 0.0;
+    info->relres_inf = worst_inf;
+    info->relres_2 = worst_2;
+    info->t_setup_ms = h->t_setup_ms;
+    info->t_factor_ms = h->t_factor_ms;
+    info->t_solve_ms = h->t_solve_ms;
+    info->bad_block = h->bad_block;
+    info->bad_row = h->bad_row;
+  }
+  if (ok) return DDPS_OK;
+  if (breakdown) return DDPS_E_BREAKDOWN;
+  return DDPS_E_NOCONV;
+}
+
+int ddps_solve(ddps_handle h, const double* f, double* x, double tol, ddps_info* info) {
+  if (!h) return DDPS_E_ARG;
+  return solve_impl(h, 1, f, h->n, x, h->n, tol, info);
+}
+
+int ddps_solve_many(ddps_handle h, int32_t k, const double* F, int64_t ldf, double* X, int64_t ldx, double tol,
+                    ddps_info* info) {
+  return solve_impl(h, k, F, ldf, X, ldx, tol, info);
+}
+
+int ddps_set_guess(ddps_handle h, const double* zhat0, int32_t k) {
+  if (!h || k < 0 || k > h->R) return DDPS_E_ARG;
+  if (k == 0 || !zhat0) {
+    h->guess_k = 0;
+    return DDPS_OK;
+  }
+  if (h->m == 0) return DDPS_OK;
+  fill_f64(h->d_guess, h->m * h->R, 0.0, h->stream);
+  HIPCHK(hipMemcpyAsync(h->d_guess, zhat0, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  // entries outside c are not unknowns of the reduced system: zero them
+  vec_apply_mask(h->m, h->R, h->d_mask, h->d_guess, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->guess_k = k;
+  return DDPS_OK;
+}
+
+int ddps_reduced_layout(ddps_handle h, int64_t* m, int64_t* c, double* mask, int32_t* t, int32_t* b) {
+  if (!h) return DDPS_E_ARG;
+  if (m) *m = h->m;
+  if (t) *t = h->t;
+  if (b) *b = h->b;
+  if (c && h->m) HIPCHK(hipMemcpyAsync(c, h->d_c, sizeof(int64_t) * h->m, hipMemcpyDeviceToDevice, h->stream));
+  if (mask && h->m)
+    HIPCHK(hipMemcpyAsync(mask, h->d_mask, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_last_reduced(ddps_handle h, double* ghat, double* zhat) {
+  if (!h) return DDPS_E_ARG;
+  const int k = std::max(1, h->last_k);
+  if (ghat && h->m) HIPCHK(hipMemcpyAsync(ghat, h->d_gh, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  if (zhat && h->m) HIPCHK(hipMemcpyAsync(zhat, h->d_zh, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_apply_preconditioner(ddps_handle h, int32_t k, const double* y, double* z, double* ghat, double* zhat,
+                              double* inner_iters) {
+  if (!h || !y || !z || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  std::vector<int> its;
+  int bk = 0;
+  const bool guess = h->opt.guess == 1 && h->guess_k > 0;
+  int rc = prec_apply(h, k, y, h->n, z, h->n, h->opt.inner_tol, guess ? 1 : 0, its, &bk);
+  if (rc) return rc;
+  if (ghat && h->m) HIPCHK(hipMemcpyAsync(ghat, h->d_gh, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  if (zhat && h->m) HIPCHK(hipMemcpyAsync(zhat, h->d_zh, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (inner_iters)
+    for (int j = 0; j < k; ++j) inner_iters[j] = its[j] / 2.0;
+  h->last_k = k;
+  return bk ? DDPS_E_BREAKDOWN : DDPS_OK;
+}
+
+int ddps_block_solve(ddps_handle h, int32_t k, const double* y, double* g) {
+  if (!h || !y || !g || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  const int R = h->R;
+  vec_to_padded(h->Np, R, h->p, h->d_blk, y, h->n, h->d_ypad, h->stream);
+  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  vec_from_padded(h->Np, R, h->p, h->d_blk, h->d_ypad, g, h->n, h->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_reduced_matvec(ddps_handle h, int32_t k, const double* x, double* v) {
+  if (!h || !x || !v || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  if (h->m == 0) return DDPS_OK;
+  HIPCHK(hipMemcpyAsync(h->d_zh, x, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  run_launch(h, h->l_zv, h->R, h->m, h->m, nullptr, nullptr, nullptr, TK_RSPMV);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(v, h->d_v, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* dst) {
+  if (!h || !dst || blk < 0 || blk >= h->p || which < 0 || which > 2) return DDPS_E_ARG;
+  const BlockInfo& B = h->blk[blk];
+  if (k < 0 || k >= B.T || (which > 0 && k >= B.T - 1)) return DDPS_E_ARG;
+  const int64_t tt = (int64_t)h->t * h->t;
+  const char* src = h->tile(blk, which, k);
+  if (h->sdt == 0) {
+    HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * tt, hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    std::vector<float> tmp(tt);
+    std::vector<double> tmp2(tt);
+    HIPCHK(hipMemcpyAsync(tmp.data(), src, sizeof(float) * tt, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int64_t q = 0; q < tt; ++q) tmp2[q] = tmp[q];
+    HIPCHK(hipMemcpyAsync(dst, tmp2.data(), sizeof(double) * tt, hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_get_spikes(ddps_handle h, int32_t blk, double* dst) {
+  if (!h || !dst || blk < 0 || blk >= h->p) return DDPS_E_ARG;
+  const BlockInfo& B = h->blk[blk];
+  const int t = h->t;
+  if (h->p == 1) {
+    fill_f64(dst, B.n * 2 * t, 0.0, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DDPS_OK;
+  }
+  const int64_t cnt = B.N * 2 * t;
+  std::vector<double> full(cnt), outv(B.n * 2 * t);
+  if (h->sdt == 0) {
+    HIPCHK(hipMemcpyAsync(full.data(), h->spike(blk, 0, 0), sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tmp(cnt);
+    HIPCHK(hipMemcpyAsync(tmp.data(), h->spike(blk, 0, 0), sizeof(float) * cnt, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int64_t q = 0; q < cnt; ++q) full[q] = tmp[q];
+  }
+  for (int64_t c = 0; c < 2 * t; ++c)
+    for (int64_t r = 0; r < B.n; ++r) outv[c * B.n + r] = full[c * B.N + B.pad + r];
+  HIPCHK(hipMemcpyAsync(dst, outv.data(), sizeof(double) * outv.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+int ddps_block_shape(ddps_handle h, int32_t* t, int32_t* tiles, int32_t* pads) {
+  if (!h) return DDPS_E_ARG;
+  if (t) *t = h->t;
+  for (int i = 0; i < h->p; ++i) {
+    if (tiles) tiles[i] = (int32_t)h->blk[i].T;
+    if (pads) pads[i] = (int32_t)h->blk[i].pad;
+  }
+  return DDPS_OK;
+}
+
+int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
+  if (!h) return DDPS_E_ARG;
+  if (block) *block = h->bad_block;
+  if (row) *row = h->bad_row;
+  return DDPS_OK;
+}
+
+int ddps_timing_enable(ddps_handle h, int32_t kind, int32_t on) {
+  if (!h || kind < 0 || kind >= TK_N) return DDPS_E_ARG;
+  h->tim_on[kind] = on != 0;
+  return DDPS_OK;
+}
+
+int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms, double* flops, double* bytes) {
+  if (!h || kind < 0 || kind >= TK_N) return DDPS_E_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double tot = 0, fl = 0, by = 0;
+  for (auto& r : h->tim[kind]) {
+    float e = 0;
+    hipEventElapsedTime(&e, r.a, r.b);
+    tot += e;
+    fl += r.flops;
+    by += r.bytes;
+    h->ev_pool.push_back(r.a);
+    h->ev_pool.push_back(r.b);
+  }
+  if (launches) *launches = (int64_t)h->tim[kind].size();
+  if (ms) *ms = tot;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  h->tim[kind].clear();
+  return DDPS_OK;
+}
+
+int ddps_memory(ddps_handle h, size_t* bytes) {
+  if (!h || !bytes) return DDPS_E_ARG;
+  *bytes = h->bytes;
+  return DDPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations shared by the host runtime (ddps.cpp) and the HIP
+// kernels.  Every bulk operation is launched as a "grouped" kernel: the host
+// builds, once per handle, a list of problem descriptors in device memory
+// (one descriptor per block and operand set), and a launch processes a
+// contiguous range of that list.  The factorisation and the solve phase are
+// fixed sequences of such launches (schedules), so they can be replayed and
+// captured in a HIP graph unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddps {
+
+// Tile edge of the grouped GEMM and of the diagonal-tile LU panel.  The
+// coupling tile size t is always a multiple of this.
+constexpr int kTile = 64;
+
+// ---------------------------------------------------------------- GEMM
+// D = C0 (+|-) op(A) op(B), column-major, M, N multiples of 64, K multiple of
+// 64 (K = 0 makes the problem a copy D = C0).
+enum GemmFlag : int32_t {
+  G_NEG = 1,      // D = C0 - A B   (else C0 + A B; without G_C0: D = -AB / AB)
+  G_C0 = 2,       // C0 is read
+  G_A_UP = 4,     // A upper triangular: only k >= row contributes
+  G_A_LO = 8,     // A lower triangular: only k <= row contributes
+  G_B_UP = 16,    // B upper triangular: only k <= col contributes
+  G_B_LO = 32,    // B lower triangular: only k >= col contributes
+  G_A_MLU = 64,   // A read as unit lower: strictly-lower entries, 1 on the diagonal, 0 above
+  G_A_MUP = 128,  // A read as upper: entries on/above the diagonal, 0 below
+  G_B_MLU = 256,
+  G_B_MUP = 512,
+};
+
+struct GemmProb {
+  const void* A;
+  const void* B;
+  const void* C0;
+  void* D;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc0, ldd;
+  int32_t flags;
+  int32_t tile0;  // first workgroup of this problem within its launch
+  int32_t pad_;
+};
+
+// ---------------------------------------------------------------- panel LU
+// In-place unpivoted LU of a 64 x 64 diagonal sub-tile followed by the
+// inversion of both triangles: on exit the strictly-lower part holds
+// L^{-1} (unit diagonal implied) and the upper part U^{-1}.
+struct PanelProb {
+  void* D;        // first element of the 64 x 64 sub-tile
+  int32_t ld;
+  int32_t block;  // block index (for pivot threshold and error report)
+  int64_t row0;   // global row of the sub-tile's first row (may be < block start: padding)
+};
+
+// ---------------------------------------------------------------- GEMV
+// y_out(rows) = y_in (+|-) A(rows, cb:ce) x  for R right-hand sides.
+// Columns [0, split) multiply x1[c], columns [split, ...) multiply x2[c-split].
+enum GemvFlag : int32_t {
+  V_NEG = 1,
+  V_YIN = 2,      // y_in is read (else treated as 0)
+  V_A_MLU = 4,    // A read as unit lower (masked)
+  V_A_MUP = 8,    // A read as upper (masked)
+  V_MASK = 16,    // the product is multiplied row-wise by mask[] before accumulation
+  V_DOT = 32,     // emit per-workgroup partials [wg][R][2] of dot(dotv, y_out) (reduced space)
+  V_DOT2 = 64,    // ... and of dot(y_out, y_out) in the second slot
+};
+
+struct GemvProb {
+  const void* A;
+  int64_t lda;
+  const double* x1;
+  const double* x2;
+  const double* yin;
+  double* yout;
+  const double* mask;   // indexed like yout rows
+  int64_t dot_off;      // offset of these output rows inside the reduced vector (V_DOT)
+  int32_t rows;         // multiple of 64
+  int32_t split;
+  int32_t cb, ce;       // column range [cb, ce) (further narrowed per slab by the masks)
+  int32_t row_skip;     // output rows < row_skip are computed but not written (padding)
+  int32_t flags;
+  int32_t wg0;          // first workgroup of this problem within its launch
+  int32_t tri;          // 0 dense, 1 lower (cols <= row), 2 upper (cols >= row): skip ranges
+};
+
+// ---------------------------------------------------------------- layout
+// Block i owns global rows [s, s+n).  It is padded on top with `pad` identity
+// rows to N = T t rows; padded row pad + j is global row s + j.  Its tiles
+// start at tile index `tiles` of the tile array: A_kk (later the inverse
+// factors) at tiles + k, L_{k+1,k} at tiles + T + k, U_{k,k+1} at
+// tiles + 2T - 1 + k.  Its spike matrix (N x 2t, leading dimension N) starts
+// at element `goff` of the spike array; padded vectors of block i start at
+// `voff`.
+struct BlockInfo {
+  int64_t s, n, pad, N, T;
+  int64_t tiles;
+  int64_t goff;
+  int64_t voff;
+};
+
+// ---------------------------------------------------------------- Krylov state
+constexpr int kMaxRhs = 8;
+constexpr int kVecGrid = 1024;  // workgroups of the grid-stride vector kernels
+enum KStatus : int32_t {
+  KS_RUNNING = 0,
+  KS_CONVERGED = 1,
+  KS_BREAKDOWN = 2,
+  KS_MAXIT = 3,
+  KS_UNUSED = 4,   // padding column of a multi-RHS batch
+};
+// Device-resident scalars of the reduced BiCGStab, one column per RHS.  A
+// field written by workgroup 0 of a kernel is read only by later kernels.
+// rho and status of iteration `it` live in slot it & 1: slot it & 1 is
+// read-only during iteration it and the iteration's last kernel writes the
+// other slot.
+struct KState {
+  double ref[kMaxRhs];       // ||g^||_2 (1 if zero)
+  double rho[2][kMaxRhs];    // rho of iteration it in slot it & 1
+  double alpha[kMaxRhs];
+  double omega[kMaxRhs];
+  double res[kMaxRhs];       // last relative residual
+  int32_t status[2][kMaxRhs];
+  int32_t iters2[kMaxRhs];   // iterations counted in half steps
+};
+
+struct Coef3 {
+  double a[kMaxRhs], b[kMaxRhs], c[kMaxRhs];
+};
+
+// Launch wrappers (kernels are in the .hip files).  `stream` is the handle's
+// stream; the problem arrays live in device memory.
+void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s);
+void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
+                  unsigned long long* bad, hipStream_t s);
+void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+                 int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
+
+void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
+                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags,
+                unsigned long long* blknorm, hipStream_t s);
+void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, const BlockInfo* blocks,
+                   const int64_t* row_ptr, const int32_t* col, const double* val, void* tiles,
+                   void* spikes, unsigned long long* colnorm, unsigned int* flags, hipStream_t s);
+void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
+                const unsigned long long* colnorm, double* mask, void* spikes, hipStream_t s);
+void setup_thresh(int p, double eps, const unsigned long long* blknorm, double* thresh, hipStream_t s);
+void fill_f64(double* ptr, int64_t count, double v, hipStream_t s);
+void fill_f32(float* ptr, int64_t count, float v, hipStream_t s);
+void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipStream_t s);
+
+void vec_to_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* y, int64_t ldy,
+                   double* yp, hipStream_t s);
+void vec_from_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* yp, double* y,
+                     int64_t ldy, hipStream_t s);
+void vec_gather_reduced(int64_t m, int R, const int64_t* rrow, const double* mask, const double* gp,
+                        int64_t Np, double* gh, hipStream_t s);
+int vec_grid(int64_t n);
+void vec_apply_mask(int64_t m, int R, const double* mask, double* x, hipStream_t s);
+void reduce2(int R, int W, const double* part, double* out, const int32_t* stop, hipStream_t s);
+void bicg_init(int R, int64_t m, int use_guess, const double* gh, double* x, const double* v, double* r,
+               double* rt, double* p, double* part, int W, hipStream_t s);
+void bicg_init_state(int R, int k, double tol, const double* sums, KState* st, hipStream_t s);
+void bicg_s(int R, int it, int64_t m, const double* s1, KState* st, const double* r, const double* v,
+            double* sv, double* part, int W, hipStream_t s);
+void bicg_xr(int R, int it, int64_t m, double tol, const double* s1, const double* s2, const double* s3,
+             KState* st, double* x, const double* p, const double* sv, const double* t, double* r,
+             const double* rt, double* part, int W, hipStream_t s);
+void bicg_p(int R, int it, int maxit, int64_t m, double tol, const double* s1, const double* s2,
+            const double* s3, const double* s4, KState* st, const double* r, double* p, const double* v,
+            int W, hipStream_t s);
+void bicg_restart(int R, int it, int64_t m, const int32_t* flag, const double* r, double* rt, double* p,
+                  double* part, int W, double* sums, KState* st, hipStream_t s);
+void csr_resid(int R, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+               const double* x, int64_t ldx, const double* f, int64_t ldf, double* r, int64_t ldr,
+               double* part, int W, double* out, hipStream_t s);
+void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
+             double* out, hipStream_t s);
+void dot2(int R, int64_t n, const double* a0, const double* b0, const double* a1, const double* b1,
+          double* part, int W, double* out, hipStream_t s);
+
+}  // namespace ddps

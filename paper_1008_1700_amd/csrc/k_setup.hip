@@ -1,0 +1,206 @@
+// Stages 1, 3 and 5 of the method on the device: validation and bandwidth of
+// the CSR input, the split A = D + R into the tile layout of each block
+// (block-tridiagonal t x t tiles, identity padding on top of short blocks),
+// the coupling entries of R_i placed as the right-hand sides of the spike
+// solves, the column inf-norms of R_i, and the dropping rule that yields the
+// index set c (as a 0/1 mask over the candidate coupling columns).
+#include "ddps_internal.h"
+#include <algorithm>
+
+namespace ddps {
+
+__device__ __forceinline__ int find_block(const int64_t* __restrict__ part, int p, int64_t r) {
+  int lo = 0, hi = p - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (part[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_scan_rows(int64_t n, int p, const int64_t* __restrict__ part,
+                            const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, int64_t nnz,
+                            unsigned long long* __restrict__ band, unsigned int* __restrict__ flags,
+                            unsigned long long* __restrict__ blknorm) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) {
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) atomicOr(flags, 1u);
+  }
+  if (r >= n) return;
+  const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+  if (b < a || a < 0 || b > nnz) { atomicOr(flags, 1u); return; }
+  const int blk = find_block(part, p, r);
+  const int64_t s = part[blk], e = part[blk + 1];
+  double rowsum = 0.0;
+  unsigned long long bw = 0;
+  unsigned int f = 0;
+  for (int64_t q = a; q < b; ++q) {
+    const int64_t c = col[q];
+    const double v = val[q];
+    if (c < 0 || c >= n) { f |= 2u; continue; }
+    if (!isfinite(v)) f |= 4u;
+    const unsigned long long d = (unsigned long long)(c > r ? c - r : r - c);
+    bw = d > bw ? d : bw;
+    if (c >= s && c < e) rowsum += fabs(v);
+  }
+  if (f) atomicOr(flags, f);
+  atomicMax(band, bw);
+  // non-negative doubles order like their bit patterns
+  atomicMax(&blknorm[blk], (unsigned long long)__double_as_longlong(rowsum));
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ part,
+                          const BlockInfo* __restrict__ blocks, const int64_t* __restrict__ row_ptr,
+                          const int32_t* __restrict__ col, const double* __restrict__ val,
+                          T* __restrict__ tiles, T* __restrict__ spikes,
+                          unsigned long long* __restrict__ colnorm, unsigned int* __restrict__ flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int blk = find_block(part, p, r);
+  const BlockInfo B = blocks[blk];
+  const int64_t tt = (int64_t)t * t;
+  const int64_t lr = B.pad + (r - B.s);
+  const int64_t kr = lr / t, rr = lr % t;
+  T* __restrict__ G = spikes + B.goff;
+  for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+    const int64_t c = col[q];
+    const double v = val[q];
+    if (c >= B.s && c < B.s + B.n) {
+      const int64_t lc = B.pad + (c - B.s);
+      const int64_t kc = lc / t, cc = lc % t;
+      int64_t tile;
+      if (kc == kr) tile = B.tiles + kr;                    // A_kk
+      else if (kc == kr + 1) tile = B.tiles + 2 * B.T - 1 + kr;  // A_{k,k+1}
+      else if (kc == kr - 1) tile = B.tiles + B.T + kc;     // A_{k+1,k}
+      else { atomicOr(flags, 8u); continue; }
+      tiles[tile * tt + cc * t + rr] += (T)v;
+    } else if (c < B.s) {
+      const int64_t jj = c - (B.s - t);
+      if (jj < 0) { atomicOr(flags, 8u); continue; }
+      G[jj * B.N + lr] += (T)v;
+      atomicMax(&colnorm[(int64_t)blk * 2 * t + jj], (unsigned long long)__double_as_longlong(fabs(v)));
+    } else {
+      const int64_t jj = c - (B.s + B.n);
+      if (jj >= t) { atomicOr(flags, 8u); continue; }
+      G[(t + jj) * B.N + lr] += (T)v;
+      atomicMax(&colnorm[(int64_t)blk * 2 * t + t + jj],
+                (unsigned long long)__double_as_longlong(fabs(v)));
+    }
+  }
+}
+
+// Identity rows on top of short blocks (padding): diagonal of tile 0.
+template <typename T>
+__global__ void k_pad_identity(int p, int t, const BlockInfo* __restrict__ blocks, T* __restrict__ tiles) {
+  const BlockInfo B = blocks[blockIdx.x];
+  for (int64_t i = threadIdx.x; i < B.pad; i += blockDim.x)
+    tiles[B.tiles * (int64_t)t * t + i * t + i] = T(1);
+}
+
+// Dropping rule (one workgroup per block): column k of R_i is kept iff
+// ||R_i(:,k)||_inf > delta * max_j ||R_i(:,j)||_inf.  Writes the reduced
+// mask and clears the right-hand sides of dropped columns.
+template <typename T>
+__global__ void k_mask(int p, int t, double delta, const BlockInfo* __restrict__ blocks,
+                       const unsigned long long* __restrict__ colnorm, double* __restrict__ mask,
+                       T* __restrict__ spikes) {
+  __shared__ double red[256];
+  const int blk = blockIdx.x;
+  const BlockInfo B = blocks[blk];
+  const unsigned long long* cn = colnorm + (int64_t)blk * 2 * t;
+  double mu = 0.0;
+  for (int j = threadIdx.x; j < 2 * t; j += blockDim.x) mu = fmax(mu, __longlong_as_double((long long)cn[j]));
+  red[threadIdx.x] = mu;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mu = red[0];
+  T* G = spikes + B.goff;
+  for (int j = threadIdx.x; j < 2 * t; j += blockDim.x) {
+    const double nrm = __longlong_as_double((long long)cn[j]);
+    const bool keep = nrm > delta * mu;
+    const bool top = j < t;
+    if (top && blk == 0) continue;
+    if (!top && blk == p - 1) continue;
+    const int64_t q = top ? (int64_t)2 * (blk - 1) * t + j : (int64_t)(2 * blk + 1) * t + (j - t);
+    mask[q] = keep ? 1.0 : 0.0;
+    if (!keep) {
+      const int64_t r0 = top ? 0 : B.N - t;
+      const int64_t r1 = top ? min((int64_t)2 * t, B.N) : B.N;
+      for (int64_t r = r0; r < r1; ++r) G[(int64_t)j * B.N + r] = T(0);
+    }
+  }
+}
+
+__global__ void k_thresh(int p, double eps, const unsigned long long* __restrict__ blknorm,
+                         double* __restrict__ thresh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p) thresh[i] = 1e3 * eps * __longlong_as_double((long long)blknorm[i]);
+}
+
+// ------------------------------------------------------------------ launchers
+void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
+                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags,
+                unsigned long long* blknorm, hipStream_t s) {
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)nb), dim3(256), 0, s, n, p, part, row_ptr, col,
+                     val, nnz, band, flags, blknorm);
+}
+
+void fill_f64(double* ptr, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t nb = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)nb), dim3(256), 0, s, ptr, count, v);
+}
+void fill_f32(float* ptr, int64_t count, float v, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t nb = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)nb), dim3(256), 0, s, ptr, count, v);
+}
+void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t nb = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3((unsigned)nb), dim3(256), 0, s, ptr, count, v);
+}
+
+void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, const BlockInfo* blocks,
+                   const int64_t* row_ptr, const int32_t* col, const double* val, void* tiles,
+                   void* spikes, unsigned long long* colnorm, unsigned int* flags, hipStream_t s) {
+  const int64_t nb = (n + 255) / 256;
+  if (dtype == 0) {
+    hipLaunchKernelGGL(k_scatter<double>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
+                       row_ptr, col, val, (double*)tiles, (double*)spikes, colnorm, flags);
+    hipLaunchKernelGGL(k_pad_identity<double>, dim3(p), dim3(256), 0, s, p, t, blocks, (double*)tiles);
+  } else {
+    hipLaunchKernelGGL(k_scatter<float>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
+                       row_ptr, col, val, (float*)tiles, (float*)spikes, colnorm, flags);
+    hipLaunchKernelGGL(k_pad_identity<float>, dim3(p), dim3(256), 0, s, p, t, blocks, (float*)tiles);
+  }
+}
+
+void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
+                const unsigned long long* colnorm, double* mask, void* spikes, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_mask<double>, dim3(p), dim3(256), 0, s, p, t, delta, blocks, colnorm, mask,
+                       (double*)spikes);
+  else
+    hipLaunchKernelGGL(k_mask<float>, dim3(p), dim3(256), 0, s, p, t, delta, blocks, colnorm, mask,
+                       (float*)spikes);
+}
+
+void setup_thresh(int p, double eps, const unsigned long long* blknorm, double* thresh, hipStream_t s) {
+  hipLaunchKernelGGL(k_thresh, dim3((p + 255) / 256), dim3(256), 0, s, p, eps, blknorm, thresh);
+}
+
+}  // namespace ddps

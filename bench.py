@@ -1,0 +1,220 @@
+"""DDPS benchmark: time-to-solution on one MI355X.
+
+A step is one pass of the whole hot path on a resident system: refresh the
+matrix values (device scan, stages 1/3/5), factor the blocks and compute the
+spikes (stages 2/4), and solve Ax = f to ||f - Ax||_inf / ||f||_inf <= tol
+(stage 6 with the Figure 2 preconditioner).  The inputs (CSR and f) are in HBM
+before the timed region starts.
+
+Workload: 3D 7-point upwind convection-diffusion, 32 x 32 x 512 grid
+(n = 524,288), velocity (1,1,10), p = 64 slabs of 8 planes (block n 8192,
+band 1024, 1024 coupling columns per side), f = A x*, x* ~ U[-1,1].
+
+The timed configuration (`value`) is the mixed-precision solver (factors and
+spikes on bf16 MFMA with split FP32 operands, FP64 refinement); the plain
+FP64 solver is timed on the same GPU in the same run for the speedup.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode M] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {"f64": 78.6e12, "f32": 157.3e12, "bf16x3": 2.5e15, "bf16": 2.5e15}
+HBM_PEAK = 8.0e12
+TOL = 1e-10
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    from workloads import configs
+    return configs.BUILDERS[name]()
+
+
+def run_mode(d, mode, steps, warmup, tol, timing_kind="gemm"):
+    import torch
+    from paper_1008_1700_amd import ddps
+    A = d["A"]
+    inner_tol = 1e-12 if mode == "f64" else 1e-7
+    S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="refine")
+    f = torch.from_numpy(np.ascontiguousarray(d["f"])).cuda()
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    val = S.val
+
+    def step():
+        ddps.ddps_refactor_values(S.h, val)
+        ddps.ddps_factor(S.h)
+        rc, info = S.solve(f, x, tol, check=False)
+        return rc, info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ddps.ddps_timing_read(S.h, timing_kind)            # clear
+    ddps.ddps_timing_enable(S.h, timing_kind, True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ddps.ddps_timing_enable(S.h, timing_kind, False)
+    tim = ddps.ddps_timing_read(S.h, timing_kind)
+    rc, info = infos[-1]
+    xs = x.cpu().numpy()
+    r = d["f"] - A.scipy() @ xs
+    out = dict(
+        mode=mode, rc=rc, ms_per_step=(t1 - t0) * 1e3 / steps,
+        factor_ms=info.t_factor_ms, solve_ms=info.t_solve_ms,
+        outer_iters=info.outer_iters, inner_iters_avg=info.inner_iters_avg,
+        applications=info.applications,
+        relres_inf=float(np.linalg.norm(r, np.inf) / np.linalg.norm(d["f"], np.inf)),
+        relerr_xstar=float(np.linalg.norm(xs - d["x_star"]) / np.linalg.norm(d["x_star"])),
+        kernel=dict(kind=timing_kind, launches_per_step=tim["launches"] / steps,
+                    ms_per_step=tim["ms"] / steps, flops_per_step=tim["flops"] / steps,
+                    bytes_per_step=tim["bytes"] / steps),
+        mem_gb=ddps.ddps_memory(S.h) / 1e9,
+    )
+    S.close()
+    del f, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def band_lu_spike_flops(d):
+    """Leading-order algorithmic flops of stages 2 and 4: 2 n_i b^2 for the
+    band LU plus 4 n_i b w_top + 2 n_i b w_bot for the spikes."""
+    b = d["b"]
+    part = d["part_ptr"]
+    p = len(part) - 1
+    tot = 0.0
+    for i in range(p):
+        ni = part[i + 1] - part[i]
+        wt = b if i > 0 else 0
+        wb = b if i < p - 1 else 0
+        tot += 2.0 * ni * b * b + 4.0 * ni * b * wt + 2.0 * ni * b * wb
+    return tot
+
+
+def cpu_baseline(d, budget_s=25.0):
+    """The CPU oracle timed on a bounded sample: block 0 of the workload,
+    exact band LU (stage 2), spikes for a subset of its coupling columns
+    (stage 4), and a block solve (6.1); scaled to the whole workload."""
+    import scipy.sparse as sp
+    from oracle import ddps_oracle as O
+    A = d["A"]
+    part = d["part_ptr"]
+    p = len(part) - 1
+    S = A.scipy()
+    lo, hi = part[0], part[1]
+    Aii = S[lo:hi, lo:hi].tocsr()
+    t0 = time.perf_counter()
+    fac = O.factor_block(Aii)
+    t_fac = time.perf_counter() - t0
+    Ri = S[lo:hi, :].tocsc()
+    cols = np.arange(hi, min(hi + d["b"], A.n))
+    ncols_total = 2 * d["b"]
+    sample = 128
+    t0 = time.perf_counter()
+    Rt = Ri[:, cols[:sample]].toarray()
+    O.block_solve(fac, Rt)
+    t_spk = (time.perf_counter() - t0) * (ncols_total / sample)
+    t0 = time.perf_counter()
+    O.block_solve(fac, np.ones(hi - lo))
+    t_sweep = time.perf_counter() - t0
+    per_block = t_fac + t_spk + t_sweep
+    total = per_block * p
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        th = max((x.get("num_threads", 1) for x in threadpool_info()), default=cores)
+    except Exception:
+        th = cores
+    return dict(value=total * 1e3, unit="ms", cores=int(th), kind="oracle",
+                sample=(f"block 0 of {p}: exact band LU, spikes for {sample} of its {ncols_total} coupling "
+                        f"columns scaled x{ncols_total // sample}, one block solve; per-block time x {p} "
+                        f"blocks (reduced solve not included); host cores available {cores}"),
+                measured_s=per_block)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="bf16x3", choices=["f64", "f32", "bf16x3", "bf16"])
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tol", type=float, default=TOL)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    log(f"building workload {args.config}")
+    d = build_workload(args.config)
+    log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
+    res = run_mode(d, args.mode, args.steps, args.warmup, args.tol)
+    log(f"{args.mode}: {json.dumps(res)}")
+    base = None
+    if not args.no_baseline and args.mode != "f64":
+        base = run_mode(d, "f64", args.steps, args.warmup, args.tol)
+        log(f"f64: {json.dumps(base)}")
+    k = res["kernel"]
+    kms = k["ms_per_step"]
+    achieved = k["flops_per_step"] / (kms * 1e-3) if kms > 0 else 0.0
+    peak = PEAKS[args.mode]
+    roof = dict(bound="mfma", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                frac=achieved / peak, traffic=None, kernel="k_gemm (grouped GEMM, factor + spikes)",
+                launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms)
+    cpu = None if args.no_cpu else cpu_baseline(d)
+    out = {
+        "metric": "DDPS time-to-solution @rel.resid 1e-10, mixed vs plain FP64 (C2 3D conv-diff 32x32x512, p=64)",
+        "value": res["ms_per_step"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "3D 7-point upwind conv-diff 32x32x512 (n=524288), v=(1,1,10), p=64 slabs "
+                               "of 8 planes, f=A x*, x*~U[-1,1], tol 1e-10",
+                   "mode": args.mode},
+        "solve": {k2: v for k2, v in res.items() if k2 != "kernel"},
+        "plain_f64": base and {k2: v for k2, v in base.items() if k2 != "kernel"},
+        "speedup_vs_f64": (base["ms_per_step"] / res["ms_per_step"]) if base else None,
+        "algorithmic_flops_factor": band_lu_spike_flops(d),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if cpu:
+        out["cpu_baseline"]["gpu_speedup"] = cpu["value"] / res["ms_per_step"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

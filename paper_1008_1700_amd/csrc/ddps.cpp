@@ -20,6 +20,8 @@
 #include "ddps_internal.h"
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -42,6 +44,7 @@ struct Launch {
   int nwg;
   double flops;
   double bytes;
+  int mode;  // GEMM tile shape: 0 = 64 x 64, 1 = 128 x 128
 };
 
 struct TimingRec {
@@ -162,9 +165,12 @@ struct ddps_ctx {
     const BlockInfo& B = blk[i];
     return (char*)d_spikes + (size_t)(B.goff + col * B.N + row) * elt;
   }
-  // scratch of block i: [WY | WA1 | WA2 | WB | WL (64 x t, ld 64) | WU (t x 64, ld t)]
+  // scratch of block i: [WY | WA1 | WA2 | WB | WL | WU]: four t x t tiles,
+  // then two t x (t/2 + 64) areas (leading dimension t) for the products of
+  // the recursive triangle inversion
+  static int64_t scratch_elems(int t) { return 4 * (int64_t)t * t + 2 * (int64_t)t * (t / 2 + 64); }
   char* scr(int i, int which) const {
-    const int64_t tt = (int64_t)t * t;
+    const int64_t tt = (int64_t)t * t, half = (int64_t)t * (t / 2 + 64);
     int64_t off = 0;
     switch (which) {
       case 0: off = 0; break;
@@ -172,7 +178,7 @@ struct ddps_ctx {
       case 2: off = 2 * tt; break;
       case 3: off = 3 * tt; break;
       case 4: off = 4 * tt; break;
-      default: off = 4 * tt + 64 * (int64_t)t; break;
+      default: off = 4 * tt + half; break;
     }
     return (char*)d_scratch + (size_t)(i * scr_per_block + off) * elt;
   }
@@ -203,16 +209,19 @@ struct ddps_ctx {
 
 namespace {
 
-double gemm_prob_flops(const GemmProb& P) {
+// Flops of a problem as executed with BT x BT tiles (the K range of each
+// tile clipped by the triangular structure, edge tiles counted at their size).
+double gemm_prob_flops(const GemmProb& P, int BM, int BN) {
   double f = 0.0;
-  for (int I0 = 0; I0 < P.M; I0 += 64)
-    for (int J0 = 0; J0 < P.N; J0 += 64) {
+  for (int I0 = 0; I0 < P.M; I0 += BM)
+    for (int J0 = 0; J0 < P.N; J0 += BN) {
       int kb = 0, ke = P.K;
       if (P.flags & G_A_UP) kb = std::max(kb, I0);
       if (P.flags & G_B_LO) kb = std::max(kb, J0);
-      if (P.flags & G_A_LO) ke = std::min(ke, I0 + 64);
-      if (P.flags & G_B_UP) ke = std::min(ke, J0 + 64);
-      if (ke > kb) f += 2.0 * 64 * 64 * (ke - kb);
+      if (P.flags & G_A_LO) ke = std::min(ke, I0 + BM);
+      if (P.flags & G_B_UP) ke = std::min(ke, J0 + BN);
+      const int mm = std::min(BM, P.M - I0), nn = std::min(BN, P.N - J0);
+      if (ke > kb) f += 2.0 * mm * nn * (ke - kb);
     }
   return f;
 }
@@ -234,14 +243,36 @@ struct ScheduleBuilder {
     flops = bytes = 0;
     off = k == LK_GEMM ? (int64_t)gemm.size() : k == LK_PANEL ? (int64_t)panel.size() : (int64_t)gemv.size();
   }
+  // GEMM launches: 128 x 128 tiles when every problem is at least that
+  // large, else 64 x 64; assigns each problem its first workgroup.
+  int finish_gemm() {
+    // 128 x 128 tiles at two workgroups per CU measured fastest for every
+    // dtype on 1024-sized problems (the 256 x 128 bf16 tile runs at one)
+    int mode = 1;
+    for (size_t q = (size_t)off; q < gemm.size(); ++q)
+      if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
+    int BM, BN;
+    gemm_tile_shape(h->gdt, mode, &BM, &BN);
+    nwg = 0;
+    flops = 0;
+    for (size_t q = (size_t)off; q < gemm.size(); ++q) {
+      GemmProb& P = gemm[q];
+      P.tile0 = nwg;
+      nwg += ((P.M + BM - 1) / BM) * ((P.N + BN - 1) / BN);
+      flops += gemm_prob_flops(P, BM, BN);
+    }
+    return mode;
+  }
   void end(std::vector<Launch>& out) {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
                                                                               : (int64_t)gemv.size()) - off;
-    if (cnt > 0 && nwg > 0) out.push_back({kind, off, (int)cnt, nwg, flops, bytes});
+    const int mode = kind == LK_GEMM ? finish_gemm() : 0;
+    if (cnt > 0 && nwg > 0) out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode});
   }
   Launch end_one() {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
-    return Launch{kind, off, (int)cnt, nwg, flops, bytes};
+    const int mode = kind == LK_GEMM ? finish_gemm() : 0;
+    return Launch{kind, off, (int)cnt, nwg, flops, bytes, mode};
   }
   void add_gemm(const void* A, int lda, const void* B, int ldb, const void* C0, int ldc0, void* D, int ldd,
                 int M, int N, int K, int flags) {
@@ -251,10 +282,8 @@ struct ScheduleBuilder {
     P.M = M; P.N = N; P.K = K;
     P.lda = lda; P.ldb = ldb; P.ldc0 = ldc0; P.ldd = ldd;
     P.flags = flags | (C0 ? G_C0 : 0);
-    P.tile0 = nwg;
-    nwg += (M / 64) * (N / 64);
-    flops += gemm_prob_flops(P);
     gemm.push_back(P);
+    nwg += 1;   // provisional: finish_gemm() assigns the tiles
   }
   void add_copy(const void* src, int lds, void* dst, int ldd, int M, int N) {
     add_gemm(nullptr, 0, nullptr, 0, src, lds, dst, ldd, M, N, 0, 0);
@@ -318,7 +347,8 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb) {
       if (k == B.T - 1 && i < p - 1) sb.add_copy(h->spike(i, (int64_t)k * t, t), N, h->scr(i, 3), t, t, t);
     }
     sb.end(S);
-    // LU of S_k with inverse triangles, 64-column panels
+    // LU of S_k, 64-column panels: panel LU (+ inverses of its 64 x 64
+    // triangles), column and row panels, trailing update
     for (int j = 0; j < Q; ++j) {
       const int j64 = j * 64, rest = t - (j + 1) * 64;
       sb.begin(LK_PANEL);
@@ -327,35 +357,68 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb) {
         sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64);
       }
       sb.end(S);
+      if (rest <= 0) continue;
       sb.begin(LK_GEMM);
       for (int i : act) {
         char* D = h->tile(i, 0, k);
-        if (rest > 0) {
-          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
-                      rest, 64, 64, G_B_MUP | G_B_UP);
-          sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
-                      64, rest, 64, G_A_MLU | G_A_LO);
-        }
-        if (j > 0) {
-          sb.add_gemm(h->sub(D, j64, 0), t, D, t, nullptr, 0, h->scr(i, 4), 64, 64, j64, j64, G_B_MLU | G_B_LO);
-          sb.add_gemm(D, t, h->sub(D, 0, j64), t, nullptr, 0, h->scr(i, 5), t, j64, 64, j64, G_A_MUP | G_A_UP);
-        }
+        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
+                    rest, 64, 64, G_B_MUP | G_B_UP);
+        sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
+                    64, rest, 64, G_A_MLU | G_A_LO);
       }
       sb.end(S);
       sb.begin(LK_GEMM);
       for (int i : act) {
         char* D = h->tile(i, 0, k);
-        if (rest > 0)
-          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
-                      h->sub(D, j64 + 64, j64 + 64), t, rest, rest, 64, G_NEG);
-        if (j > 0) {
-          sb.add_gemm(h->sub(D, j64, j64), t, h->scr(i, 4), 64, nullptr, 0, h->sub(D, j64, 0), t, 64, j64, 64,
-                      G_NEG | G_A_MLU | G_A_LO);
-          sb.add_gemm(h->scr(i, 5), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, 0, j64), t, j64, 64, 64,
-                      G_NEG | G_B_MUP | G_B_UP);
-        }
+        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
+                    h->sub(D, j64 + 64, j64 + 64), t, rest, rest, 64, G_NEG);
       }
       sb.end(S);
+    }
+    // inverse triangles of the whole tile by recursive halving of the panel
+    // range: for a split [lo, mid) | [mid, hi) whose halves are inverted,
+    //   X10 = -X11 (L10 X00),   Y01 = -(Y00 U01) Y11
+    // (X = L^{-1}, Y = U^{-1}); all splits of one depth, over all blocks,
+    // share a launch pair.
+    {
+      std::vector<std::vector<std::array<int, 3>>> levels;
+      std::function<void(int, int, int)> rec = [&](int lo, int hi, int d) {
+        if (hi - lo <= 1) return;
+        const int mid = (lo + hi) / 2;
+        if ((int)levels.size() <= d) levels.resize(d + 1);
+        levels[d].push_back({lo, mid, hi});
+        rec(lo, mid, d + 1);
+        rec(mid, hi, d + 1);
+      };
+      rec(0, Q, 0);
+      for (int d = (int)levels.size() - 1; d >= 0; --d) {
+        sb.begin(LK_GEMM);
+        for (int i : act) {
+          char* D = h->tile(i, 0, k);
+          for (auto& c : levels[d]) {
+            const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
+            const int m0 = mid - lo, m1 = hi - mid;
+            sb.add_gemm(h->sub(D, mid, lo), t, h->sub(D, lo, lo), t, nullptr, 0, h->scr(i, 4) + (size_t)mid * h->elt, t,
+                        m1, m0, m0, G_B_MLU | G_B_LO);
+            sb.add_gemm(h->sub(D, lo, lo), t, h->sub(D, lo, mid), t, nullptr, 0, h->scr(i, 5) + (size_t)lo * h->elt, t,
+                        m0, m1, m0, G_A_MUP | G_A_UP);
+          }
+        }
+        sb.end(S);
+        sb.begin(LK_GEMM);
+        for (int i : act) {
+          char* D = h->tile(i, 0, k);
+          for (auto& c : levels[d]) {
+            const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
+            const int m0 = mid - lo, m1 = hi - mid;
+            sb.add_gemm(h->sub(D, mid, mid), t, h->scr(i, 4) + (size_t)mid * h->elt, t, nullptr, 0, h->sub(D, mid, lo), t,
+                        m1, m0, m1, G_NEG | G_A_MLU | G_A_LO);
+            sb.add_gemm(h->scr(i, 5) + (size_t)lo * h->elt, t, h->sub(D, mid, mid), t, nullptr, 0, h->sub(D, lo, mid), t,
+                        m0, m1, m1, G_NEG | G_B_MUP | G_B_UP);
+          }
+        }
+        sb.end(S);
+      }
     }
     // post(k): off-diagonal factors and forward spike sweep
     sb.begin(LK_GEMM);
@@ -558,7 +621,7 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
   hipEvent_t a;
   h->tim_begin(tkind, a);
   switch (L.kind) {
-    case LK_GEMM: launch_gemm(h->gdt, 0, h->d_gemm + L.off, L.nprob, L.nwg, h->stream); break;
+    case LK_GEMM: launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, h->stream); break;
     case LK_PANEL:
       launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, h->stream);
       break;
@@ -918,7 +981,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->nspike = goff;
   h->Np = voff;
   h->m = p > 1 ? (int64_t)2 * t * (p - 1) : 0;
-  h->scr_per_block = 4 * (int64_t)t * t + 128 * (int64_t)t;
+  h->scr_per_block = ddps_ctx::scratch_elems(t);
   // memory plan (F1 check before the large allocations)
   const int R = h->R;
   const int64_t m = h->m;
@@ -1094,10 +1157,14 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       if (!conv_col(j, ri[j])) return false;
     return true;
   };
+  // inner tolerance of one application: opt.inner_tol, relaxed (never beyond
+  // 1e-2) when the current residual is already small, since an application
+  // then only has to reduce it by tol * ||f|| / ||r||
+  double itol = h->opt.inner_tol;
   auto papply = [&](const double* y, double* z) -> int {
     // the guess seeds the reduced solve of the first application only; later
     // applications act on residuals, for which it is no approximation
-    int r = prec_apply(h, k, y, n, z, n, h->opt.inner_tol, (guess && apps == 0) ? 1 : 0, its, &bk);
+    int r = prec_apply(h, k, y, n, z, n, itol, (guess && apps == 0) ? 1 : 0, its, &bk);
     if (r) return r;
     ++apps;
     for (int j = 0; j < k; ++j) inner_total += its[j];
@@ -1107,6 +1174,11 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   if (h->opt.outer_method == 1) {
     // iterative refinement: x += P^{-1} (f - A x)
     while (!all_conv(rinf) && outer < h->opt.outer_maxit) {
+      double worst = 0.0;   // largest ||r||/||f|| still above the tolerance
+      for (int j = 0; j < k; ++j)
+        if (fnorm[j] > 0) worst = std::max(worst, rinf[j] / fnorm[j]);
+      itol = h->opt.inner_tol;
+      if (worst > 0) itol = std::min(1e-2, std::max(itol, 0.1 * tol / worst));
       if ((rc = papply(h->d_ro, h->d_z))) return rc;
       // columns already converged keep their x
       Coef3 cf{};

@@ -133,6 +133,7 @@ struct Coef3 {
 // Launch wrappers (kernels are in the .hip files).  `stream` is the handle's
 // stream; the problem arrays live in device memory.
 void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s);
+void gemm_tile_shape(int dtype, int mode, int* bm, int* bn);
 void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
                   unsigned long long* bad, hipStream_t s);
 void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,

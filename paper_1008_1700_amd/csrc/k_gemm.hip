@@ -1,17 +1,19 @@
 // Grouped GEMM on CDNA4 matrix cores: D = C0 +/- op(A) op(B) over a list of
 // independent problems (one launch covers every block of the partition).
 //
-// Workgroup tile 64 x 64, 256 threads = 4 waves, each wave a 32 x 32 sub-tile
-// made of 2 x 2 MFMA 16x16 blocks.  K advances in chunks of 16 (f64/f32) or 32
-// (bf16) staged through LDS with one register prefetch stage.  Operands are
-// column-major (LAPACK layout).  Triangular operands are exploited twice:
-// the K range of each output tile is clipped to where both operands can be
-// nonzero, and masked loads read the unit-lower / upper halves of the packed
-// inverse tiles.
+// Workgroup tile BM x BN (64 x 64 or 128 x 128), 256 threads = 4 waves in a
+// 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA
+// blocks.  K advances in chunks (16 for f64/f32, 32 for bf16) staged through
+// LDS, with the next chunk's global loads in flight while the current chunk
+// is multiplied.  Operands are column-major (LAPACK layout); M and N need
+// only be multiples of 64 (a 128-tile on the edge is masked).  Triangular
+// operands are exploited twice: the K range of each output tile is clipped
+// to where both operands can be nonzero, and masked loads read the
+// unit-lower / upper halves of the packed inverse tiles.
 //
 // The MFMA is fed with B^T as its first and A^T as its second operand, so it
 // accumulates D^T: the 16 lanes of a lane group hold 16 consecutive rows of
-// one column of D, and the stores to the column-major D are 128-byte (f64)
+// one column of D, and the stores to the column-major D are 64-128-byte
 // segments.
 #include "ddps_internal.h"
 
@@ -20,6 +22,7 @@ namespace ddps {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // Logical workgroup index such that each XCD (hardware dispatches workgroups
 // round-robin over the 8 XCDs) receives one contiguous range of tiles: tiles
@@ -39,11 +42,13 @@ __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int
   return lo;
 }
 
+// Value of op(X)(r, c) given the stored value v: masks of the packed inverse
+// tiles and zero outside the problem (rows >= rmax or columns >= cmax).
 template <typename T>
-__device__ __forceinline__ T masked(T v, int r, int c, int flags_lu, int flags_up) {
-  if (flags_lu) return r > c ? v : (r == c ? T(1) : T(0));
-  if (flags_up) return r <= c ? v : T(0);
-  return v;
+__device__ __forceinline__ T select_op(T v, int r, int c, bool lu, bool up, int rmax, int cmax) {
+  if (lu) v = r > c ? v : (r == c ? T(1) : T(0));
+  if (up) v = r <= c ? v : T(0);
+  return (r < rmax && c < cmax) ? v : T(0);
 }
 
 template <typename T> struct Mma;
@@ -64,70 +69,80 @@ template <> struct Mma<float> {
   }
 };
 
+struct TileCoord {
+  int I0, J0, kb, ke;
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ TileCoord tile_of(const GemmProb& P, int wg) {
+  const int tiles_m = (P.M + BM - 1) / BM;
+  const int local = wg - P.tile0;
+  TileCoord t;
+  t.I0 = (local % tiles_m) * BM;
+  t.J0 = (local / tiles_m) * BN;
+  const int fl = P.flags;
+  t.kb = 0;
+  t.ke = P.K;
+  if (fl & G_A_UP) t.kb = max(t.kb, t.I0);
+  if (fl & G_B_LO) t.kb = max(t.kb, t.J0);
+  if (fl & G_A_LO) t.ke = min(t.ke, t.I0 + BM);
+  if (fl & G_B_UP) t.ke = min(t.ke, t.J0 + BN);
+  return t;
+}
+
 // ------------------------------------------------------------------------
 // f64 / f32: K chunk 16, one MFMA 16x16x4 per (k4, mi, ni).
 // ------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_std(const GemmProb* __restrict__ probs, int nprob) {
-  constexpr int BK = 16, LDP = 64 + 4;
-  __shared__ T As[2][BK][LDP];
-  __shared__ T Bs[2][BK][LDP];
+template <typename T, int BM, int BN, int BK = 16, int OCC = 1>
+__global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restrict__ probs, int nprob) {
+  constexpr int PADL = 4;
+  constexpr int MB = BM / 32, NB = BN / 32;          // 16x16 blocks per wave
+  constexpr int AE = BM * BK / 256, BE = BN * BK / 256;  // elements per thread
+  __shared__ T As[2][BK][BM + PADL];
+  __shared__ T Bs[2][BK][BN + PADL];
   using acc_t = typename Mma<T>::acc;
 
   const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
-  const int tiles_m = P.M >> 6;
-  const int local = wg - P.tile0;
-  const int I0 = (local % tiles_m) << 6;
-  const int J0 = (local / tiles_m) << 6;
+  const TileCoord tc = tile_of<BM, BN>(P, wg);
+  const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
   const int fl = P.flags;
-
-  int kb = 0, ke = P.K;
-  if (fl & G_A_UP) kb = max(kb, I0);
-  if (fl & G_B_LO) kb = max(kb, J0);
-  if (fl & G_A_LO) ke = min(ke, I0 + 64);
-  if (fl & G_B_UP) ke = min(ke, J0 + 64);
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const T* __restrict__ A = (const T*)P.A;
   const T* __restrict__ B = (const T*)P.B;
-  const int a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
 
-  acc_t acc[2][2];
+  acc_t acc[MB][NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  // A chunk: 64 rows x 16 k; thread -> (m = tid&63, kk = tid>>6 + 4i)
-  // B chunk: 16 k x 64 cols; thread -> (kk = tid&15, n = tid>>4 + 16i)
-  const int am = tid & 63, ak = tid >> 6;
-  const int bk = tid & 15, bn = tid >> 4;
-  T ra[4], rb[4];
+  // A chunk BM x 16: thread -> row m = tid % BM, k = tid / BM + (256/BM) i
+  // B chunk 16 x BN: thread -> col n = tid % BN, k = (tid / BN) * BE + i  (BE consecutive k)
+  constexpr int ASTEP = 256 / BM;
+  static_assert(AE * ASTEP == BK, "A chunk mapping");
+  const int am = tid % BM, ak = tid / BM;
+  const int bn = tid % BN, bk0 = (tid / BN) * BE;
+  const int arow = min(I0 + am, P.M - 1);
+  const int bcol = min(J0 + bn, P.N - 1);
+  T ra[AE], rb[BE];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = I0 + am, c = k0 + ak + 4 * i;
-      T v = T(0);
-      const bool need = a_lu ? (r > c) : (a_up ? (r <= c) : true);
-      if (need) v = A[(int64_t)c * P.lda + r];
-      ra[i] = masked(v, r, c, a_lu, a_up);
+    for (int i = 0; i < AE; ++i) {
+      const int c = k0 + ak + ASTEP * i;
+      ra[i] = select_op(A[(int64_t)c * P.lda + arow], I0 + am, c, a_lu, a_up, P.M, 1 << 30);
     }
+    const T* bp = B + (int64_t)bcol * P.ldb + k0 + bk0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = k0 + bk, c = J0 + bn + 16 * i;
-      T v = T(0);
-      const bool need = b_lu ? (r > c) : (b_up ? (r <= c) : true);
-      if (need) v = B[(int64_t)c * P.ldb + r];
-      rb[i] = masked(v, r, c, b_lu, b_up);
-    }
+    for (int i = 0; i < BE; ++i) rb[i] = select_op(bp[i], k0 + bk0 + i, J0 + bn, b_lu, b_up, 1 << 30, P.N);
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) As[buf][ak + 4 * i][am] = ra[i];
+    for (int i = 0; i < AE; ++i) As[buf][ak + ASTEP * i][am] = ra[i];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Bs[buf][bk][bn + 16 * i] = rb[i];
+    for (int i = 0; i < BE; ++i) Bs[buf][bk0 + i][bn] = rb[i];
   };
 
   if (kb < ke) {
@@ -141,15 +156,15 @@ __global__ __launch_bounds__(256) void k_gemm_std(const GemmProb* __restrict__ p
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         const int kk = k4 * 4 + (lane >> 4);
-        T xa[2], xb[2];
+        T xa[NB], xb[MB];
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni) xa[ni] = Bs[cur][kk][wn * 32 + ni * 16 + (lane & 15)];
+        for (int ni = 0; ni < NB; ++ni) xa[ni] = Bs[cur][kk][wn * (BN / 2) + ni * 16 + (lane & 15)];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) xb[mi] = As[cur][kk][wm * 32 + mi * 16 + (lane & 15)];
+        for (int mi = 0; mi < MB; ++mi) xb[mi] = As[cur][kk][wm * (BM / 2) + mi * 16 + (lane & 15)];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = Mma<T>::run(xa[ni], xb[mi], acc[mi][ni]);
+          for (int ni = 0; ni < NB; ++ni) acc[mi][ni] = Mma<T>::run(xa[ni], xb[mi], acc[mi][ni]);
       }
       if (more) store(cur ^ 1);
       __syncthreads();
@@ -158,165 +173,219 @@ __global__ __launch_bounds__(256) void k_gemm_std(const GemmProb* __restrict__ p
   }
 
   // Epilogue: lane holds D[row = .. + (lane&15)][col = .. + Mma::row(lane, v)]
-  // (the MFMA computed D^T, so its rows are D's columns)
   const T* __restrict__ C0 = (const T*)P.C0;
   T* __restrict__ D = (T*)P.D;
   const bool has_c0 = fl & G_C0, neg = fl & G_NEG;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < NB; ++ni)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = I0 + wm * 32 + mi * 16 + (lane & 15);
-        const int c = J0 + wn * 32 + ni * 16 + Mma<T>::row(lane, v);
-        T val = acc[mi][ni][v];
-        if (neg) val = -val;
-        if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
-        D[(int64_t)c * P.ldd + r] = val;
+        const int r = I0 + wm * (BM / 2) + mi * 16 + (lane & 15);
+        const int c = J0 + wn * (BN / 2) + ni * 16 + Mma<T>::row(lane, v);
+        if (r < P.M && c < P.N) {
+          T val = acc[mi][ni][v];
+          if (neg) val = -val;
+          if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
+          D[(int64_t)c * P.ldd + r] = val;
+        }
       }
 }
 
 // ------------------------------------------------------------------------
-// bf16 MFMA (16x16x32, FP32 accumulation) on FP32-stored operands.  With
+// bf16 MFMA (32x32x16, FP32 accumulation) on FP32-stored operands.  With
 // SPLIT each FP32 operand x is written as hi + lo, hi = bf16(x),
 // lo = bf16(x - hi), and the product is hi*hi + hi*lo + lo*hi (the lo*lo
-// term is below FP32 rounding of the result's leading part).
+// term lies below the FP32 rounding of the result).  The split is done once
+// per element while the chunk is staged into LDS, in layout [row][k] with k
+// contiguous, so each MFMA operand is one 16-byte LDS read.
+//
+// MFMA 32x32x16 bf16 lane layout (measured): operand X (32 x 16) lane l
+// holds X[l%32][8(l/32) .. +8), operand Y (16 x 32) lane l holds
+// Y[8(l/32) .. +8)[l%32]; accumulator register v of lane l is element
+// (8(v/4) + 4(l/32) + v%4, l%32).
 // ------------------------------------------------------------------------
-__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
-  constexpr int BK = 32;
-  constexpr int LDK = BK + 8;  // k-contiguous rows of 32 bf16, padded
-  __shared__ __bf16 Ah[64][LDK];
-  __shared__ __bf16 Bh[64][LDK];
-  __shared__ __bf16 Al[SPLIT ? 64 : 1][LDK];
-  __shared__ __bf16 Bl[SPLIT ? 64 : 1][LDK];
+template <bool SPLIT, int BM, int BN, int OCC = 1>
+__global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
+  constexpr int BK = 32, LDK = BK + 8;
+  constexpr int MB = BM / 64, NB = BN / 64;     // 32 x 32 blocks per wave (wave tile BM/2 x BN/2)
+  constexpr int NS = SPLIT ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) __bf16 As[NS][BM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BN][LDK];
 
   const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
-  const int tiles_m = P.M >> 6;
-  const int local = wg - P.tile0;
-  const int I0 = (local % tiles_m) << 6;
-  const int J0 = (local / tiles_m) << 6;
+  const TileCoord tc = tile_of<BM, BN>(P, wg);
+  const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
   const int fl = P.flags;
-  int kb = 0, ke = P.K;
-  if (fl & G_A_UP) kb = max(kb, I0);
-  if (fl & G_B_LO) kb = max(kb, J0);
-  if (fl & G_A_LO) ke = min(ke, I0 + 64);
-  if (fl & G_B_UP) ke = min(ke, J0 + 64);
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const float* __restrict__ A = (const float*)P.A;
   const float* __restrict__ B = (const float*)P.B;
-  const int a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_edge = I0 + BM > P.M, b_edge = J0 + BN > P.N;
 
-  f32x4 acc[2][2];
+  f32x16 acc[MB][NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  // A chunk 64 x 32: thread -> (m = tid&63, k = tid>>6 + 4i), i < 8
-  // B chunk 32 x 64: thread -> (k = tid&31, n = tid>>5 + 8i), i < 8
-  const int am = tid & 63, ak = tid >> 6;
-  const int bk = tid & 31, bn = tid >> 5;
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    float ra[8], rb[8];
+  // A chunk BM x 32: thread -> 4 consecutive rows (a float4 per k) x AK k.
+  // B chunk 32 x BN: thread -> one column, BKT consecutive k (float4 loads).
+  constexpr int AROWG = BM / 4;
+  constexpr int AK = BK * AROWG / 256;
+  constexpr int BKT = BK * BN / 256;
+  const int arg = tid % AROWG, akg = tid / AROWG;
+  const int ar = I0 + 4 * arg;
+  const int bn = tid % BN, bkg = tid / BN;
+  const int bc = J0 + bn;
+  const int arow_ld = min(ar, P.M - 4);
+  const int bcol_ld = min(bc, P.N - 1);
+  float4 ra[AK];
+  float4 rb[BKT / 4];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = I0 + am, c = k0 + ak + 4 * i;
-      float v = 0.f;
-      const bool need = a_lu ? (r > c) : (a_up ? (r <= c) : true);
-      if (need) v = A[(int64_t)c * P.lda + r];
-      ra[i] = masked(v, r, c, a_lu, a_up);
-    }
+    for (int i = 0; i < AK; ++i)
+      ra[i] = *(const float4*)(A + (int64_t)(k0 + akg * AK + i) * P.lda + arow_ld);
+    const float* bp = B + (int64_t)bcol_ld * P.ldb + k0 + bkg * BKT;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = k0 + bk, c = J0 + bn + 8 * i;
-      float v = 0.f;
-      const bool need = b_lu ? (r > c) : (b_up ? (r <= c) : true);
-      if (need) v = B[(int64_t)c * P.ldb + r];
-      rb[i] = masked(v, r, c, b_lu, b_up);
-    }
-    __syncthreads();
+    for (int i = 0; i < BKT / 4; ++i) rb[i] = *(const float4*)(bp + 4 * i);
+  };
+  typedef __bf16 bfa __attribute__((ext_vector_type(AK)));
+  auto store_chunk = [&](int k0) {
+    // masks only where the chunk crosses a packed triangle's diagonal or the edge
+    const bool am = a_edge || ((a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM);
+    const bool bm = b_edge || ((b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const __bf16 h = to_bf16(ra[i]);
-      Ah[am][ak + 4 * i] = h;
-      if (SPLIT) Al[am][ak + 4 * i] = to_bf16(ra[i] - (float)h);
-    }
+    for (int q = 0; q < 4; ++q) {
+      const int r = ar + q;
+      bfa h, l;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const __bf16 h = to_bf16(rb[i]);
-      Bh[bn + 8 * i][bk] = h;
-      if (SPLIT) Bl[bn + 8 * i][bk] = to_bf16(rb[i] - (float)h);
-    }
-    __syncthreads();
-    // MFMA 16x16x32 bf16: operand X (16 x 32): lane holds row lane&15,
-    // k = 8*(lane>>4) .. +8; operand Y (32 x 16): lane holds col lane&15,
-    // the same k range.  X = B^T block, Y = A^T block.
-    const int kk = 8 * (lane >> 4);
-    bf16x8 xh[2], yh[2], xl[2], yl[2];
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      const int n = wn * 32 + ni * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        xh[ni][e] = Bh[n][kk + e];
-        if (SPLIT) xl[ni][e] = Bl[n][kk + e];
+      for (int i = 0; i < AK; ++i) {
+        float x = ra[i][q];
+        if (am) x = select_op(x, r, k0 + akg * AK + i, a_lu, a_up, P.M, 1 << 30);
+        h[i] = (__bf16)x;
+        if (SPLIT) l[i] = (__bf16)(x - (float)h[i]);
       }
+      *(bfa*)&As[0][4 * arg + q][akg * AK] = h;
+      if (SPLIT) *(bfa*)&As[NS - 1][4 * arg + q][akg * AK] = l;
     }
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi) {
-      const int m = wm * 32 + mi * 16 + (lane & 15);
+    for (int i4 = 0; i4 < BKT / 4; ++i4) {
+      bf16x4 h, l;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        yh[mi][e] = Ah[m][kk + e];
-        if (SPLIT) yl[mi][e] = Al[m][kk + e];
+      for (int q = 0; q < 4; ++q) {
+        float x = rb[i4][q];
+        if (bm) x = select_op(x, k0 + bkg * BKT + 4 * i4 + q, bc, b_lu, b_up, 1 << 30, P.N);
+        h[q] = (__bf16)x;
+        if (SPLIT) l[q] = (__bf16)(x - (float)h[q]);
       }
+      *(bf16x4*)&Bs[0][bn][bkg * BKT + 4 * i4] = h;
+      if (SPLIT) *(bf16x4*)&Bs[NS - 1][bn][bkg * BKT + 4 * i4] = l;
     }
+  };
+
+  if (kb < ke) {
+    load(kb);
+    for (int kcur = kb; kcur < ke; kcur += BK) {
+      __syncthreads();             // previous chunk's LDS reads are done
+      store_chunk(kcur);
+      __syncthreads();
+      if (kcur + BK < ke) load(kcur + BK);
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+      for (int ks = 0; ks < BK / 16; ++ks) {
+        const int kk = ks * 16 + 8 * (lane >> 5);
+        bf16x8 xh[NB], xl[NB], yh[MB], yl[MB];
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
-        if (SPLIT) {
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[ni], yh[mi], acc[mi][ni], 0, 0, 0);
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[ni], yl[mi], acc[mi][ni], 0, 0, 0);
+        for (int ni = 0; ni < NB; ++ni) {
+          const int n = wn * (BN / 2) + ni * 32 + (lane & 31);
+          xh[ni] = *(const bf16x8*)&Bs[0][n][kk];
+          if (SPLIT) xl[ni] = *(const bf16x8*)&Bs[NS - 1][n][kk];
         }
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[ni], yh[mi], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+        for (int mi = 0; mi < MB; ++mi) {
+          const int m = wm * (BM / 2) + mi * 32 + (lane & 31);
+          yh[mi] = *(const bf16x8*)&As[0][m][kk];
+          if (SPLIT) yl[mi] = *(const bf16x8*)&As[NS - 1][m][kk];
+        }
+#pragma unroll
+        for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NB; ++ni) {
+            if (SPLIT) {
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ni], yh[mi], acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yl[mi], acc[mi][ni], 0, 0, 0);
+            }
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yh[mi], acc[mi][ni], 0, 0, 0);
+          }
       }
+    }
   }
 
+  // Epilogue: lane holds D[row = .. + (lane&31)][col = .. + 8(v/4) + 4(lane/32) + v%4]
   const float* __restrict__ C0 = (const float*)P.C0;
   float* __restrict__ D = (float*)P.D;
   const bool has_c0 = fl & G_C0, neg = fl & G_NEG;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < NB; ++ni)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = I0 + wm * 32 + mi * 16 + (lane & 15);
-        const int c = J0 + wn * 32 + ni * 16 + 4 * (lane >> 4) + v;
-        float val = acc[mi][ni][v];
-        if (neg) val = -val;
-        if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
-        D[(int64_t)c * P.ldd + r] = val;
+      for (int v = 0; v < 16; ++v) {
+        const int r = I0 + wm * (BM / 2) + mi * 32 + (lane & 31);
+        const int c = J0 + wn * (BN / 2) + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (r < P.M && c < P.N) {
+          float val = acc[mi][ni][v];
+          if (neg) val = -val;
+          if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
+          D[(int64_t)c * P.ldd + r] = val;
+        }
       }
 }
 
+// mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only)
 void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s) {
-  (void)mode;
   if (nwg <= 0 || nprob <= 0) return;
-  switch (dtype) {
-    case 0: hipLaunchKernelGGL(k_gemm_std<double>, dim3(nwg), dim3(256), 0, s, probs, nprob); break;
-    case 1: hipLaunchKernelGGL(k_gemm_std<float>, dim3(nwg), dim3(256), 0, s, probs, nprob); break;
-    case 2: hipLaunchKernelGGL(k_gemm_bf16<true>, dim3(nwg), dim3(256), 0, s, probs, nprob); break;
-    default: hipLaunchKernelGGL(k_gemm_bf16<false>, dim3(nwg), dim3(256), 0, s, probs, nprob); break;
+  const dim3 g(nwg), b(256);
+  // two workgroups per CU (two waves per SIMD) measured best for f64/f32
+  if (dtype <= 1) {
+    if (mode >= 1) {
+      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 128, 128, 16, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_std<float, 128, 128, 16, 2>), g, b, 0, s, probs, nprob);
+    } else {
+      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 64, 64, 16, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_std<float, 64, 64, 16, 2>), g, b, 0, s, probs, nprob);
+    }
+    return;
   }
+  const bool split = dtype == 2;
+  switch (mode) {
+    case 2:
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128>), g, b, 0, s, probs, nprob);
+      break;
+    case 1:
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2>), g, b, 0, s, probs, nprob);
+      break;
+    default:
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 64, 64, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 64, 64, 2>), g, b, 0, s, probs, nprob);
+      break;
+  }
+}
+
+// tile edge (rows, columns) of a launch mode
+void gemm_tile_shape(int dtype, int mode, int* bm, int* bn) {
+  if (mode == 2 && dtype >= 2) { *bm = 256; *bn = 128; }
+  else if (mode >= 1) { *bm = 128; *bn = 128; }
+  else { *bm = 64; *bn = 64; }
 }
 
 }  // namespace ddps

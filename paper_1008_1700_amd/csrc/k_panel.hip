@@ -1,7 +1,24 @@
-// Diagonal sub-tile kernel of the blocked block-LU: for each problem, one
-// workgroup loads a 64 x 64 sub-tile into LDS, factors it without pivoting
-// (A = L U, L unit lower), then inverts both triangles and writes back
-// L^{-1} strictly below the diagonal and U^{-1} on and above it.
+// Diagonal sub-tile kernel of the tile LU: for each problem, one wave (64
+// threads) factors a 64 x 64 sub-tile without pivoting (A = L U, L unit
+// lower), then inverts both triangles in place and writes back L^{-1}
+// strictly below the diagonal and U^{-1} on and above it.
+//
+// Lane r owns row r of the sub-tile in registers.  Elimination step k: lane
+// k publishes row k of U in LDS, every lane r > k forms its multiplier
+// l = a(r,k) / u(k,k) (kept in place, and saved in LDS as column k of L),
+// and updates its row.  A single wave needs no cross-wave barrier between
+// steps (the LDS operations of one wave complete in order); with four waves
+// the two barriers per step dominated this latency-bound kernel.
+//
+// Inversion, all in the lane's own row (no communication), using the saved
+// L columns and U rows:
+//   X = L^{-1}, columns j from right to left:
+//       X(r,j) = -( L(r,j) + sum_{j<l<r} X(r,l) L(l,j) )
+//   Y = U^{-1}, columns j from left to right:
+//       Y(j,j) = 1/u(j,j);  Y(r,j) = -( sum_{r<=l<j} Y(r,l) U(l,j) ) / u(j,j)
+// (the Y sums read Y(r,l) for l < j, already final since columns go left to
+// right; the X sums read X(r,l) for l > j, final since columns go right to
+// left; both read the factors from LDS, never from other lanes).
 //
 // Pivot check: a pivot u_kk with |u_kk| <= thresh[block] (or not finite)
 // records (block, global row) in *bad through an atomic minimum, so the
@@ -11,72 +28,84 @@
 namespace ddps {
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ probs,
-                                               const double* __restrict__ thresh,
-                                               unsigned long long* __restrict__ bad) {
-  constexpr int N = kTile, LD = kTile + 1;
-  __shared__ T S[N][LD];   // S[row][col]
-  __shared__ T X[N][LD];   // inverses: X[r][c], r > c from L^{-1}, r <= c from U^{-1}
+__global__ __launch_bounds__(64) void k_panel(const PanelProb* __restrict__ probs,
+                                              const double* __restrict__ thresh,
+                                              unsigned long long* __restrict__ bad) {
+  constexpr int N = kTile, LD = kTile + 4;
+  __shared__ __attribute__((aligned(16))) T Ur[N][LD];   // Ur[k][c] = U(k, c), c >= k
+  __shared__ __attribute__((aligned(16))) T Lc[N][LD];   // Lc[k][r] = L(r, k), r > k
   const PanelProb P = probs[blockIdx.x];
   T* __restrict__ D = (T*)P.D;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < N * N; e += 256) {
-    const int r = e & (N - 1), c = e >> 6;
-    S[r][c] = D[(int64_t)c * P.ld + r];
-  }
-  __syncthreads();
+  const int r = threadIdx.x;
+  T a[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) a[c] = D[(int64_t)c * P.ld + r];
   const double th = thresh[P.block];
+
+  // Every loop is fully unrolled: register indices are compile-time
+  // constants and the triangular loop bounds prune at compile time.
+#pragma unroll
   for (int k = 0; k < N; ++k) {
-    const T piv = S[k][k];
-    if (tid == 0) {
-      const double a = fabs((double)piv);
-      if (!(a > th) || !(a <= 1.7e308)) {
+    if (r == k) {
+#pragma unroll
+      for (int c = k; c < N; ++c) Ur[k][c] = a[c];
+    }
+    __syncthreads();   // a single wave: orders the LDS accesses only
+    const T piv = Ur[k][k];
+    if (r == 0) {
+      const double av = fabs((double)piv);
+      if (!(av > th) || !(av <= 1.7e308)) {
         const unsigned long long key =
             ((unsigned long long)P.block << 40) | (unsigned long long)(P.row0 + k);
         atomicMin(bad, key);
       }
     }
-    if (tid > k && tid < N) S[tid][k] = S[tid][k] / piv;
-    __syncthreads();
-    const int m = N - 1 - k;
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = k + 1 + e % m, c = k + 1 + e / m;
-      S[r][c] -= S[r][k] * S[k][c];
-    }
-    __syncthreads();
-  }
-  // Wave 0: column c of L^{-1} (forward substitution, unit diagonal implied).
-  // Wave 1: column c of U^{-1} (back substitution).
-  if (tid < N) {
-    const int c = tid;
-    for (int r = c + 1; r < N; ++r) {
-      T s = S[r][c];
-      for (int l = c + 1; l < r; ++l) s += S[r][l] * X[l][c];
-      X[r][c] = -s;
-    }
-  } else if (tid < 2 * N) {
-    const int c = tid - N;
-    X[c][c] = T(1) / S[c][c];
-    for (int r = c - 1; r >= 0; --r) {
-      T s = T(0);
-      for (int l = r + 1; l <= c; ++l) s += S[r][l] * X[l][c];
-      X[r][c] = -s / S[r][r];
+    if (r > k) {
+      const T l = a[k] / piv;
+      Lc[k][r] = l;
+      a[k] = l;
+#pragma unroll
+      for (int c = k + 1; c < N; ++c) a[c] -= l * Ur[k][c];
     }
   }
   __syncthreads();
-  for (int e = tid; e < N * N; e += 256) {
-    const int r = e & (N - 1), c = e >> 6;
-    D[(int64_t)c * P.ld + r] = X[r][c];
+
+  // X = L^{-1} in the strictly lower part, columns right to left
+#pragma unroll
+  for (int j = N - 2; j >= 0; --j) {
+    if (r > j) {
+      T acc = a[j];
+#pragma unroll
+      for (int l = j + 1; l < N - 1; ++l)
+        if (l < r) acc += a[l] * Lc[j][l];
+      a[j] = -acc;
+    }
   }
+  // Y = U^{-1} in the upper part, columns left to right
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const T d = T(1) / Ur[j][j];
+    if (r < j) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < j; ++l)
+        if (l >= r) acc += a[l] * Ur[l][j];
+      a[j] = -acc * d;
+    } else if (r == j) {
+      a[j] = d;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < N; ++c) D[(int64_t)c * P.ld + r] = a[c];
 }
 
 void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
                   unsigned long long* bad, hipStream_t s) {
   if (nprob <= 0) return;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_panel<double>, dim3(nprob), dim3(256), 0, s, probs, thresh, bad);
+    hipLaunchKernelGGL(k_panel<double>, dim3(nprob), dim3(64), 0, s, probs, thresh, bad);
   else
-    hipLaunchKernelGGL(k_panel<float>, dim3(nprob), dim3(256), 0, s, probs, thresh, bad);
+    hipLaunchKernelGGL(k_panel<float>, dim3(nprob), dim3(64), 0, s, probs, thresh, bad);
 }
 
 }  // namespace ddps

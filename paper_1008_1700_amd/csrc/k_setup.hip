@@ -18,36 +18,67 @@ __device__ __forceinline__ int find_block(const int64_t* __restrict__ part, int 
   return lo;
 }
 
-__global__ void k_scan_rows(int64_t n, int p, const int64_t* __restrict__ part,
-                            const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                            const double* __restrict__ val, int64_t nnz,
-                            unsigned long long* __restrict__ band, unsigned int* __restrict__ flags,
-                            unsigned long long* __restrict__ blknorm) {
+// One thread per row; band, flags and per-block norms are reduced inside the
+// workgroup first (rows of a workgroup nearly always share one block), so
+// only a few atomics per workgroup reach memory.
+__global__ __launch_bounds__(256) void k_scan_rows(int64_t n, int p, const int64_t* __restrict__ part,
+                                                   const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, int64_t nnz,
+                                                   unsigned long long* __restrict__ band,
+                                                   unsigned int* __restrict__ flags,
+                                                   unsigned long long* __restrict__ blknorm) {
+  __shared__ unsigned long long sb[256];
+  __shared__ double sn[256];
+  __shared__ unsigned int sf[256];
+  __shared__ int sblk[256];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r == 0) {
-    if (row_ptr[0] != 0 || row_ptr[n] != nnz) atomicOr(flags, 1u);
-  }
-  if (r >= n) return;
-  const int64_t a = row_ptr[r], b = row_ptr[r + 1];
-  if (b < a || a < 0 || b > nnz) { atomicOr(flags, 1u); return; }
-  const int blk = find_block(part, p, r);
-  const int64_t s = part[blk], e = part[blk + 1];
-  double rowsum = 0.0;
   unsigned long long bw = 0;
   unsigned int f = 0;
-  for (int64_t q = a; q < b; ++q) {
-    const int64_t c = col[q];
-    const double v = val[q];
-    if (c < 0 || c >= n) { f |= 2u; continue; }
-    if (!isfinite(v)) f |= 4u;
-    const unsigned long long d = (unsigned long long)(c > r ? c - r : r - c);
-    bw = d > bw ? d : bw;
-    if (c >= s && c < e) rowsum += fabs(v);
+  double rowsum = 0.0;
+  int blk = -1;
+  if (r == 0 && (row_ptr[0] != 0 || row_ptr[n] != nnz)) f |= 1u;
+  if (r < n) {
+    const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+    blk = find_block(part, p, r);
+    if (b < a || a < 0 || b > nnz) {
+      f |= 1u;
+    } else {
+      const int64_t s = part[blk], e = part[blk + 1];
+      for (int64_t q = a; q < b; ++q) {
+        const int64_t c = col[q];
+        const double v = val[q];
+        if (c < 0 || c >= n) { f |= 2u; continue; }
+        if (!isfinite(v)) f |= 4u;
+        const unsigned long long d = (unsigned long long)(c > r ? c - r : r - c);
+        bw = d > bw ? d : bw;
+        if (c >= s && c < e) rowsum += fabs(v);
+      }
+    }
   }
-  if (f) atomicOr(flags, f);
-  atomicMax(band, bw);
-  // non-negative doubles order like their bit patterns
-  atomicMax(&blknorm[blk], (unsigned long long)__double_as_longlong(rowsum));
+  const int t = threadIdx.x;
+  sb[t] = bw; sf[t] = f; sn[t] = rowsum; sblk[t] = blk;
+  __syncthreads();
+  const int b0 = sblk[0];
+  int blast = -1;
+  for (int i = blockDim.x - 1; i >= 0; --i)
+    if (sblk[i] >= 0) { blast = sblk[i]; break; }
+  const bool one_block = b0 >= 0 && b0 == blast;
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) {
+      sb[t] = sb[t] > sb[t + s2] ? sb[t] : sb[t + s2];
+      sf[t] |= sf[t + s2];
+      if (one_block) sn[t] = fmax(sn[t], sn[t + s2]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (sf[0]) atomicOr(flags, sf[0]);
+    atomicMax(band, sb[0]);
+    // non-negative doubles order like their bit patterns
+    if (one_block) atomicMax(&blknorm[b0], (unsigned long long)__double_as_longlong(sn[0]));
+  }
+  if (!one_block && blk >= 0) atomicMax(&blknorm[blk], (unsigned long long)__double_as_longlong(rowsum));
 }
 
 template <typename T>

@@ -44,15 +44,15 @@ def build_workload(name):
     return configs.BUILDERS[name]()
 
 
-def run_mode(d, mode, steps, warmup, tol, timing_kind="gemm"):
+def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None):
     import torch
     from paper_1008_1700_amd import ddps
     A = d["A"]
-    inner_tol = 1e-12 if mode == "f64" else 1e-7
     S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="refine")
     f = torch.from_numpy(np.ascontiguousarray(d["f"])).cuda()
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     val = S.val
+    tune = ddps.ddps_autotune(S.h)        # execution form (stream groups, tile policy), untimed
 
     def step():
         ddps.ddps_refactor_values(S.h, val)
@@ -76,6 +76,16 @@ def run_mode(d, mode, steps, warmup, tol, timing_kind="gemm"):
     tim = ddps.ddps_timing_read(S.h, timing_kind)
     rc, info = infos[-1]
     xs = x.cpu().numpy()
+    graph_ms = None
+    if graph_steps:
+        ddps.ddps_set_execution(S.h, tune["streams"], True, tune["tile_policy"])
+        step()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(graph_steps):
+            step()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) * 1e3 / graph_steps
     r = d["f"] - A.scipy() @ xs
     out = dict(
         mode=mode, rc=rc, ms_per_step=(t1 - t0) * 1e3 / steps,
@@ -88,6 +98,8 @@ def run_mode(d, mode, steps, warmup, tol, timing_kind="gemm"):
                     ms_per_step=tim["ms"] / steps, flops_per_step=tim["flops"] / steps,
                     bytes_per_step=tim["bytes"] / steps),
         mem_gb=ddps.ddps_memory(S.h) / 1e9,
+        inner_tol=inner_tol,
+        exec=dict(tune, graph_ms_per_step=graph_ms),
     )
     S.close()
     del f, x
@@ -164,6 +176,10 @@ def main():
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol", type=float, default=TOL)
+    # defaults: the fastest tolerance of a sweep for each mode on this workload
+    ap.add_argument("--inner-tol", type=float, default=1e-6, help="reduced-solve tolerance, timed mode")
+    ap.add_argument("--inner-tol-f64", type=float, default=1e-9, help="reduced-solve tolerance, FP64 mode")
+    ap.add_argument("--graph-steps", type=int, default=2, help="extra steps timed with the factor graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -174,19 +190,29 @@ def main():
     log(f"building workload {args.config}")
     d = build_workload(args.config)
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
-    res = run_mode(d, args.mode, args.steps, args.warmup, args.tol)
+    itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
+    res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps)
     log(f"{args.mode}: {json.dumps(res)}")
     base = None
     if not args.no_baseline and args.mode != "f64":
-        base = run_mode(d, "f64", args.steps, args.warmup, args.tol)
+        base = run_mode(d, "f64", args.steps, args.warmup, args.tol, args.inner_tol_f64,
+                        graph_steps=args.graph_steps)
         log(f"f64: {json.dumps(base)}")
     k = res["kernel"]
     kms = k["ms_per_step"]
     achieved = k["flops_per_step"] / (kms * 1e-3) if kms > 0 else 0.0
     peak = PEAKS[args.mode]
+    # achieved: flops the grouped GEMM launches execute (triangular K ranges
+    # clipped at tile granularity) over their summed launch durations; with
+    # stream groups launches overlap, so this understates the rate.  The
+    # phase rate divides the band-LU + spike algorithmic flops by the factor
+    # phase's wall time.
+    alg = band_lu_spike_flops(d)
     roof = dict(bound="mfma", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                frac=achieved / peak, traffic=None, kernel="k_gemm (grouped GEMM, factor + spikes)",
-                launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms)
+                frac=achieved / peak, traffic=None, kernel="k_gemm_bf16 / k_gemm_std (grouped GEMM, factor + spikes)",
+                launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms,
+                flops_per_step=k["flops_per_step"],
+                factor_phase_rate=alg / (res["factor_ms"] * 1e-3) / 1e12)
     cpu = None if args.no_cpu else cpu_baseline(d)
     out = {
         "metric": "DDPS time-to-solution @rel.resid 1e-10, mixed vs plain FP64 (C2 3D conv-diff 32x32x512, p=64)",

@@ -76,6 +76,9 @@ typedef struct {
   int32_t max_rhs;         /* largest k passed to ddps_solve_many (>= 1) */
   size_t mem_budget;       /* bytes the handle may allocate; 0 = free device memory */
   void* stream;            /* hipStream_t on which all work is ordered */
+  int32_t factor_streams;  /* stream groups of the factorisation (blocks assigned longest
+                              first); 0 = automatic */
+  int32_t factor_graph;    /* 1: ddps_factor is captured once as a HIP graph and replayed */
 } ddps_options;
 
 typedef struct {
@@ -93,7 +96,8 @@ typedef struct {
 
 /* Fills *opt with the defaults: delta 0, FP64 factors, inner_tol 1e-12,
  * inner_maxit 1000, outer_maxit 1000, iterative refinement, zero guess,
- * max_rhs 1, no memory budget, null stream. */
+ * max_rhs 1, no memory budget, null stream, automatic stream groups, no
+ * graph. */
 void ddps_default_options(ddps_options* opt);
 
 /* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row
@@ -197,6 +201,26 @@ int ddps_block_shape(ddps_handle h, int32_t* t, int32_t* tiles, int32_t* pads);
 /* Block and global row of the first bad pivot found by the last ddps_factor
  * (host pointers; -1 if none). */
 int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
+
+/* Execution form of ddps_factor (the method's result does not depend on it):
+ * streams = stream groups over which the blocks are distributed (blocks of
+ * different groups factor concurrently; 0 = automatic), graph = 1 to capture
+ * the factorisation once as a HIP graph and replay it, tile_policy = 0 for
+ * 128 x 128 GEMM tiles where every problem of a launch allows them, 1 for
+ * 64 x 64 tiles only.  Rebuilds the launch schedules; call before
+ * ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM, DDPS_E_HIP. */
+int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
+
+/* Autotuner of the execution form: times ddps_factor on the device for
+ * stream groups {1, 2, 4, 8} (at most p) and both tile policies, keeps the
+ * fastest, and records it in the JSON file cache_path (may be NULL) under a
+ * key made of the GPU architecture, factor dtype, tile size t, p and the
+ * largest tile-row count; a later call with the same key takes the cached
+ * choice without timing.  Host outputs (may be NULL): chosen streams, tile
+ * policy and its factor time in milliseconds.  The handle is left factored
+ * with the chosen form. */
+int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy,
+                  double* factor_ms);
 
 /* Per-kernel timing for roofline reporting.  ddps_timing_enable(h, kind, 1)
  * records HIP events around every launch of that kernel kind on the handle's

@@ -112,8 +112,20 @@ struct ddps_ctx {
   // host staging (pinned)
   KState* h_state = nullptr;
   double* h_out = nullptr;
-  // schedules
-  std::vector<Launch> sch_factor, sch_fwd, sch_bwd, sch_retr;
+  // schedules: the factorisation is split over stream groups of blocks
+  std::vector<std::vector<Launch>> sch_group;
+  std::vector<int> group_of;
+  std::vector<Launch> sch_fwd, sch_bwd, sch_retr;
+  int groups = 1;          // stream groups of the factor schedule
+  int tile_policy = 0;     // 0: 128 x 128 GEMM tiles where every problem allows, 1: 64 x 64 only
+  bool use_graph = false;  // capture ddps_factor once as a HIP graph, then replay it
+  hipStream_t fstream = nullptr;          // internal stream of the factorisation
+  std::vector<hipStream_t> gstream;       // one per group beyond the first
+  std::vector<hipEvent_t> gevent;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool capturing = false;
   Launch l_pv{}, l_st{}, l_zv{};  // reduced products: p->v (dot r~), s->t (dots), z->v
   int W1 = 0;
   bool factored = false;
@@ -183,17 +195,34 @@ struct ddps_ctx {
     return (char*)d_scratch + (size_t)(i * scr_per_block + off) * elt;
   }
 
-  void tim_begin(int kind, hipEvent_t& a) {
+  void tim_begin(int kind, hipEvent_t& a, hipStream_t s) {
     a = nullptr;
-    if (!tim_on[kind]) return;
+    if (!tim_on[kind] || capturing) return;
     a = get_event();
-    hipEventRecord(a, stream);
+    hipEventRecord(a, s);
   }
-  void tim_end(int kind, hipEvent_t a, double flops, double bytes_) {
+  void tim_begin(int kind, hipEvent_t& a) { tim_begin(kind, a, stream); }
+  void tim_end(int kind, hipEvent_t a, double flops, double bytes_, hipStream_t s) {
     if (!a) return;
     hipEvent_t b2 = get_event();
-    hipEventRecord(b2, stream);
+    hipEventRecord(b2, s);
     tim[kind].push_back({a, b2, flops, bytes_});
+  }
+  void tim_end(int kind, hipEvent_t a, double flops, double bytes_) { tim_end(kind, a, flops, bytes_, stream); }
+  void free_ptr(void* q) {
+    if (!q) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == q) {
+        allocs.erase(allocs.begin() + i);
+        break;
+      }
+    hipFree(q);
+  }
+  void drop_graph() {
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    if (graph) hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
   }
   hipEvent_t get_event() {
     if (!ev_pool.empty()) {
@@ -248,7 +277,7 @@ struct ScheduleBuilder {
   int finish_gemm() {
     // 128 x 128 tiles at two workgroups per CU measured fastest for every
     // dtype on 1024-sized problems (the 256 x 128 bf16 tile runs at one)
-    int mode = 1;
+    int mode = h->tile_policy == 1 ? 0 : 1;
     for (size_t q = (size_t)off; q < gemm.size(); ++q)
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
     int BM, BN;
@@ -318,12 +347,15 @@ int fac_dtype_code(int d) {
   }
 }
 
-void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb) {
+// Factor schedule of the blocks in `members` (ascending), appended to S.
+void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<int>& members,
+                           std::vector<Launch>& S) {
   const int t = h->t, p = h->p, Q = t / 64;
-  auto& S = h->sch_factor;
-  for (int k = 0; k < h->Tmax; ++k) {
+  int Tmax = 0;
+  for (int i : members) Tmax = std::max<int>(Tmax, (int)h->blk[i].T);
+  for (int k = 0; k < Tmax; ++k) {
     std::vector<int> act;
-    for (int i = 0; i < p; ++i)
+    for (int i : members)
       if (h->blk[i].T > k) act.push_back(i);
     // pre(k): Schur update, top-spike right-hand side, staging copies
     sb.begin(LK_GEMM);
@@ -439,9 +471,9 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb) {
   }
   // backward spike sweep over all spike columns
   if (p > 1) {
-    for (int s = 0; s < h->Tmax; ++s) {
+    for (int s = 0; s < Tmax; ++s) {
       std::vector<int> act;
-      for (int i = 0; i < p; ++i)
+      for (int i : members)
         if (h->blk[i].T > s) act.push_back(i);
       sb.begin(LK_GEMM);
       for (int i : act) {
@@ -617,27 +649,31 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
 }
 
 int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, const double* dotv,
-               double* partial, const int32_t* stop, int tkind) {
+               double* partial, const int32_t* stop, int tkind, hipStream_t s) {
   hipEvent_t a;
-  h->tim_begin(tkind, a);
+  h->tim_begin(tkind, a, s);
   switch (L.kind) {
-    case LK_GEMM: launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, h->stream); break;
-    case LK_PANEL:
-      launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, h->stream);
-      break;
-    default:
-      launch_gemv(h->sdt, R, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, h->stream);
-      break;
+    case LK_GEMM: launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, s); break;
+    case LK_PANEL: launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, s); break;
+    default: launch_gemv(h->sdt, R, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s); break;
   }
-  h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV ? R : 1), L.bytes);
+  h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV ? R : 1), L.bytes, s);
   return DDPS_OK;
+}
+int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, const double* dotv,
+               double* partial, const int32_t* stop, int tkind) {
+  return run_launch(h, L, R, ldx, ldy, dotv, partial, stop, tkind, h->stream);
 }
 
 int rhs_alloc(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; }
 
+// Default number of stream groups: enough to overlap one group's
+// latency-bound panel launches with the others' GEMMs, while each group
+// still has several blocks per launch.
+int default_groups(const ddps_ctx* h) { return std::max(1, std::min(4, h->p / 8)); }
+
 // ---------------------------------------------------------------- phases
-int do_scatter(ddps_ctx* h) {
-  hipStream_t s = h->stream;
+int do_scatter(ddps_ctx* h, hipStream_t s) {
   const int64_t tcount = h->ntiles * (int64_t)h->t * h->t;
   if (h->sdt == 0) {
     fill_f64((double*)h->d_tiles, tcount, 0.0, s);
@@ -655,12 +691,96 @@ int do_scatter(ddps_ctx* h) {
   return DDPS_OK;
 }
 
-int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, int64_t ldy, int tk_gemv) {
+int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, int64_t ldy, int tk_gemv,
+                 hipStream_t s) {
   for (const Launch& L : S) {
     const int tk = L.kind == LK_GEMM ? TK_GEMM : L.kind == LK_PANEL ? TK_PANEL : tk_gemv;
-    run_launch(h, L, R, ldx, ldy, nullptr, nullptr, nullptr, tk);
+    run_launch(h, L, R, ldx, ldy, nullptr, nullptr, nullptr, tk, s);
   }
   HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, int64_t ldy, int tk_gemv) {
+  return run_schedule(h, S, R, ldx, ldy, tk_gemv, h->stream);
+}
+
+// Stages 1-5 on the internal factor stream: scatter, then every group's
+// schedule on its own stream (fork/join through events).
+int enqueue_factor(ddps_ctx* h) {
+  hipStream_t f = h->fstream;
+  int rc = do_scatter(h, f);
+  if (rc) return rc;
+  const int G = (int)h->sch_group.size();
+  if (G <= 1) return G == 1 ? run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f) : DDPS_OK;
+  HIPCHK(hipEventRecord(h->fork_ev, f));
+  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->gstream[g - 1], h->fork_ev, 0));
+  if ((rc = run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f))) return rc;
+  for (int g = 1; g < G; ++g) {
+    if ((rc = run_schedule(h, h->sch_group[g], 1, 0, 0, TK_GEMM, h->gstream[g - 1]))) return rc;
+    HIPCHK(hipEventRecord(h->gevent[g - 1], h->gstream[g - 1]));
+  }
+  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(f, h->gevent[g - 1], 0));
+  return DDPS_OK;
+}
+
+// Blocks to groups, longest first (LPT: each block, in decreasing number of
+// tile rows, goes to the group with the least work so far); then the
+// factor schedules of all groups and the solve schedules, uploaded.
+int build_schedules(ddps_ctx* h) {
+  const int p = h->p;
+  const int G = std::max(1, std::min(h->groups, p));
+  std::vector<int> order(p);
+  for (int i = 0; i < p; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->blk[a].T > h->blk[b].T; });
+  std::vector<int64_t> load(G, 0);
+  h->group_of.assign(p, 0);
+  for (int i : order) {
+    int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    h->group_of[i] = g;
+    load[g] += h->blk[i].T;
+  }
+  ScheduleBuilder sb;
+  sb.h = h;
+  h->sch_group.assign(G, {});
+  for (int g = 0; g < G; ++g) {
+    std::vector<int> mem;
+    for (int i = 0; i < p; ++i)
+      if (h->group_of[i] == g) mem.push_back(i);
+    build_factor_schedule(h, sb, mem, h->sch_group[g]);
+  }
+  h->sch_fwd.clear();
+  h->sch_bwd.clear();
+  h->sch_retr.clear();
+  build_solve_schedules(h, sb);
+  h->free_ptr(h->d_gemm);
+  h->free_ptr(h->d_panel);
+  h->free_ptr(h->d_gemv);
+  h->d_gemm = nullptr;
+  h->d_panel = nullptr;
+  h->d_gemv = nullptr;
+  int rc;
+  if ((rc = h->alloc(h->d_gemm, (int64_t)sb.gemm.size())) || (rc = h->alloc(h->d_panel, (int64_t)sb.panel.size())) ||
+      (rc = h->alloc(h->d_gemv, (int64_t)sb.gemv.size())))
+    return rc;
+  hipStream_t s = h->stream;
+  if (!sb.gemm.empty())
+    HIPCHK(hipMemcpyAsync(h->d_gemm, sb.gemm.data(), sizeof(GemmProb) * sb.gemm.size(), hipMemcpyHostToDevice, s));
+  if (!sb.panel.empty())
+    HIPCHK(hipMemcpyAsync(h->d_panel, sb.panel.data(), sizeof(PanelProb) * sb.panel.size(), hipMemcpyHostToDevice, s));
+  if (!sb.gemv.empty())
+    HIPCHK(hipMemcpyAsync(h->d_gemv, sb.gemv.data(), sizeof(GemvProb) * sb.gemv.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // streams and events of the groups
+  while ((int)h->gstream.size() < G - 1) {
+    hipStream_t gs;
+    hipEvent_t ge;
+    HIPCHK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ge, hipEventDisableTiming));
+    h->gstream.push_back(gs);
+    h->gevent.push_back(ge);
+  }
+  h->drop_graph();
+  if ((int64_t)h->W1 * h->R * 2 > h->part_cap) return DDPS_E_ARG;
   return DDPS_OK;
 }
 
@@ -851,6 +971,8 @@ void ddps_default_options(ddps_options* o) {
   o->max_rhs = 1;
   o->mem_budget = 0;
   o->stream = nullptr;
+  o->factor_streams = 0;
+  o->factor_graph = 0;
 }
 
 const char* ddps_status_string(int s) {
@@ -876,6 +998,16 @@ void ddps_destroy(ddps_handle h) {
       hipEventDestroy(r.b);
     }
   for (auto e : h->ev_pool) hipEventDestroy(e);
+  h->drop_graph();
+  if (h->fstream) hipStreamSynchronize(h->fstream);
+  for (auto gs : h->gstream) {
+    hipStreamSynchronize(gs);
+    hipStreamDestroy(gs);
+  }
+  for (auto ge : h->gevent) hipEventDestroy(ge);
+  if (h->fstream) hipStreamDestroy(h->fstream);
+  if (h->fork_ev) hipEventDestroy(h->fork_ev);
+  if (h->join_ev) hipEventDestroy(h->join_ev);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (void* q : h->allocs) hipFree(q);
@@ -1055,22 +1187,14 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     return fail(DDPS_E_HIP);
   const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
   setup_thresh(p, eps, h->d_blknorm, h->d_thresh, s);
-  // schedules
-  ScheduleBuilder sb;
-  sb.h = h;
-  build_factor_schedule(h, sb);
-  build_solve_schedules(h, sb);
-  if ((rc = h->alloc(h->d_gemm, (int64_t)sb.gemm.size())) || (rc = h->alloc(h->d_panel, (int64_t)sb.panel.size())) ||
-      (rc = h->alloc(h->d_gemv, (int64_t)sb.gemv.size())))
-    return fail(rc);
-  if ((!sb.gemm.empty() && hipMemcpyAsync(h->d_gemm, sb.gemm.data(), sizeof(GemmProb) * sb.gemm.size(),
-                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
-      (!sb.panel.empty() && hipMemcpyAsync(h->d_panel, sb.panel.data(), sizeof(PanelProb) * sb.panel.size(),
-                                           hipMemcpyHostToDevice, s) != hipSuccess) ||
-      (!sb.gemv.empty() && hipMemcpyAsync(h->d_gemv, sb.gemv.data(), sizeof(GemvProb) * sb.gemv.size(),
-                                          hipMemcpyHostToDevice, s) != hipSuccess))
+  // execution resources and schedules
+  if (hipStreamCreateWithFlags(&h->fstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess)
     return fail(DDPS_E_HIP);
-  if ((int64_t)h->W1 * R * 2 > h->part_cap) return fail(DDPS_E_ARG);
+  h->groups = o.factor_streams > 0 ? o.factor_streams : default_groups(h);
+  h->use_graph = o.factor_graph != 0;
+  if ((rc = build_schedules(h))) return fail(rc);
   hipEventRecord(h->ev1, s);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(DDPS_E_HIP);
   float ms = 0;
@@ -1083,10 +1207,33 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
 int ddps_factor(ddps_handle h) {
   if (!h) return DDPS_E_ARG;
   hipEventRecord(h->ev0, h->stream);
-  int rc = do_scatter(h);
-  if (rc) return rc;
-  rc = run_schedule(h, h->sch_factor, 1, 0, 0, TK_GEMM);
-  if (rc) return rc;
+  // the factorisation runs on the internal stream, ordered after the
+  // caller's stream and joined back into it
+  HIPCHK(hipEventRecord(h->fork_ev, h->stream));
+  HIPCHK(hipStreamWaitEvent(h->fstream, h->fork_ev, 0));
+  if (h->use_graph) {
+    if (!h->graph_exec) {
+      h->capturing = true;
+      hipError_t e = hipStreamBeginCapture(h->fstream, hipStreamCaptureModeThreadLocal);
+      int rc = e == hipSuccess ? enqueue_factor(h) : DDPS_E_HIP;
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(h->fstream, &g);
+      h->capturing = false;
+      if (rc || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        last_hip_error() = e2;
+        return rc ? rc : DDPS_E_HIP;
+      }
+      h->graph = g;
+      HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(h->graph_exec, h->fstream));
+  } else {
+    int rc = enqueue_factor(h);
+    if (rc) return rc;
+  }
+  HIPCHK(hipEventRecord(h->join_ev, h->fstream));
+  HIPCHK(hipStreamWaitEvent(h->stream, h->join_ev, 0));
   hipEventRecord(h->ev1, h->stream);
   unsigned long long bad = 0;
   unsigned int flags = 0;
@@ -1465,6 +1612,121 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
   if (!h) return DDPS_E_ARG;
   if (block) *block = h->bad_block;
   if (row) *row = h->bad_row;
+  return DDPS_OK;
+}
+
+int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
+  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 1) return DDPS_E_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipStreamSynchronize(h->fstream));
+  h->groups = streams > 0 ? streams : default_groups(h);
+  h->use_graph = graph != 0;
+  h->tile_policy = tile_policy;
+  h->factored = false;   // the factors must be recomputed with the new form
+  return build_schedules(h);
+}
+
+namespace {
+
+std::string tune_key(ddps_ctx* h) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch = arch.substr(0, c);
+  }
+  static const char* dt[] = {"f64", "f32", "bf16x3", "bf16"};
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/%s/t%d/p%d/T%d", arch.c_str(), dt[h->gdt], h->t, h->p, h->Tmax);
+  return buf;
+}
+
+// The cache is a flat JSON object {"key": {"streams": s, "tile_policy": q,
+// "factor_ms": ms}, ...} written and read by this file only.
+bool cache_lookup(const char* path, const std::string& key, int* streams, int* policy, double* ms) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string txt;
+  char b[4096];
+  size_t nr;
+  while ((nr = std::fread(b, 1, sizeof(b), f)) > 0) txt.append(b, nr);
+  std::fclose(f);
+  const size_t at = txt.find("\"" + key + "\"");
+  if (at == std::string::npos) return false;
+  int s2 = 0, q2 = 0;
+  double m2 = 0;
+  const size_t br = txt.find('{', at);
+  if (br == std::string::npos) return false;
+  if (std::sscanf(txt.c_str() + br, "{\"streams\": %d, \"tile_policy\": %d, \"factor_ms\": %lf", &s2, &q2, &m2) != 3)
+    return false;
+  *streams = s2;
+  *policy = q2;
+  *ms = m2;
+  return true;
+}
+
+void cache_store(const char* path, const std::string& key, int streams, int policy, double ms) {
+  if (!path) return;
+  std::vector<std::string> entries;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+      std::string l(line);
+      if (l.find("\"streams\"") != std::string::npos && l.find("\"" + key + "\"") == std::string::npos) {
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+        entries.push_back(l);
+      }
+    }
+    std::fclose(f);
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "  \"%s\": {\"streams\": %d, \"tile_policy\": %d, \"factor_ms\": %.3f}", key.c_str(),
+                streams, policy, ms);
+  entries.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i) std::fprintf(f, "%s%s\n", entries[i].c_str(), i + 1 < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy, double* factor_ms) {
+  if (!h) return DDPS_E_ARG;
+  const std::string key = tune_key(h);
+  int bs = 0, bq = 0;
+  double bms = 0;
+  int rc;
+  if (!cache_lookup(cache_path, key, &bs, &bq, &bms)) {
+    bms = 1e300;
+    for (int q = 0; q <= 1; ++q)
+      for (int g : {1, 2, 4, 8}) {
+        if (g > h->p) continue;
+        if ((rc = ddps_set_execution(h, g, 0, q))) return rc;
+        if ((rc = ddps_factor(h))) return rc;       // warm-up
+        if ((rc = ddps_factor(h))) return rc;
+        if (h->t_factor_ms < bms) {
+          bms = h->t_factor_ms;
+          bs = g;
+          bq = q;
+        }
+      }
+    cache_store(cache_path, key, bs, bq, bms);
+  }
+  const int graph = h->use_graph ? 1 : 0;
+  if ((rc = ddps_set_execution(h, bs, graph, bq))) return rc;
+  if ((rc = ddps_factor(h))) return rc;
+  if (streams) *streams = bs;
+  if (tile_policy) *tile_policy = bq;
+  if (factor_ms) *factor_ms = bms;
   return DDPS_OK;
 }
 

@@ -42,6 +42,8 @@ class ddps_options(ctypes.Structure):
         ("max_rhs", ctypes.c_int32),
         ("mem_budget", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("factor_streams", ctypes.c_int32),
+        ("factor_graph", ctypes.c_int32),
     ]
 
 
@@ -89,6 +91,8 @@ _SIGS = {
     "ddps_get_spikes": (_I32, [_P, _I32, _P]),
     "ddps_block_shape": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "ddps_last_singular": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
+    "ddps_set_execution": (_I32, [_P, _I32, _I32, _I32]),
+    "ddps_autotune": (_I32, [_P, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
     "ddps_timing_enable": (_I32, [_P, _I32, _I32]),
     "ddps_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D),
                                 ctypes.POINTER(_D)]),
@@ -238,6 +242,19 @@ def ddps_last_singular(h):
     return b.value, r.value
 
 
+def ddps_set_execution(h, streams=0, graph=False, tile_policy=0):
+    _chk(lib().ddps_set_execution(h, int(streams), 1 if graph else 0, int(tile_policy)), "ddps_set_execution")
+
+
+def ddps_autotune(h, cache_path=None):
+    s = ctypes.c_int32()
+    q = ctypes.c_int32()
+    ms = ctypes.c_double()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _chk(lib().ddps_autotune(h, path, ctypes.byref(s), ctypes.byref(q), ctypes.byref(ms)), "ddps_autotune")
+    return dict(streams=s.value, tile_policy=q.value, factor_ms=ms.value)
+
+
 def ddps_timing_enable(h, kind, on=True):
     _chk(lib().ddps_timing_enable(h, TIMING_KINDS.get(kind, kind), 1 if on else 0), "ddps_timing_enable")
 
@@ -273,7 +290,7 @@ class Solver:
 
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
-                 mem_budget=0):
+                 mem_budget=0, streams=0, graph=False):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -287,6 +304,8 @@ class Solver:
         o.max_rhs = int(max_rhs)
         o.guess = 1 if guess else 0
         o.mem_budget = int(mem_budget)
+        o.factor_streams = int(streams)
+        o.factor_graph = 1 if graph else 0
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

@@ -15,6 +15,7 @@ spikes on bf16 MFMA with split FP32 operands, FP64 refinement); the plain
 FP64 solver is timed on the same GPU in the same run for the speedup.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode M] [--no-cpu]
+       python bench.py --config c4 [--mode M]   (learned-guess time sequence)
 """
 from __future__ import annotations
 
@@ -166,6 +167,55 @@ def cpu_baseline(d, budget_s=25.0):
                 measured_s=per_block)
 
 
+def run_c4(args):
+    """C4: 300 implicit-Euler steps of 2D convection-diffusion on 1024^2 with a
+    rotating velocity, p = 64.  Steps 1..200 solve with the previous-step
+    guess and record training pairs; the network trains on the GPU; steps
+    201..300 are solved with both guesses from the same factors."""
+    import torch
+    from paper_1008_1700_amd import ddps, guess
+    from workloads import configs, pde
+    nx = ny = 1024
+    p = 64
+    A1, _ = configs.c4_matrix(1, nx, ny)
+    part = pde.slab_partition(ny, ny // p, nx)
+    kinds = configs.c4_kinds(A1, nx)
+    itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
+    S = ddps.Solver(A1, part, dtype=args.mode, inner_tol=itol, outer="refine", guess=True)
+    tune = ddps.ddps_autotune(S.h)
+    log(f"c4: n={A1.n} p={p} mode={args.mode} exec={tune}")
+    t0 = time.perf_counter()
+    out = guess.run_sequence(S, lambda st: configs.c4_step_values(st, kinds, nx), steps=args.c4_steps,
+                             train_steps=args.c4_train, dt=configs.C4_DT, source=1.0, tol=args.tol,
+                             hidden=512, epochs=args.c4_epochs, batch_rows=512, lr=1e-3, seed=0, log=log)
+    wall = time.perf_counter() - t0
+    S.close()
+    recs = out["records"]
+    ev = [r for r in recs if "r_learn" in r]
+    mean = lambda k, rs: float(np.mean([r[k] for r in rs])) if rs else None
+    res = {
+        "metric": "C4 learned initial guess: reduced-solve start residual and solve time per step, "
+                  "learned (judged) vs previous-step guess, steps after training",
+        "value": mean("learn_ms", ev), "unit": "ms", "higher_is_better": False,
+        "n_gpus": 1, "dtype": {"f64": "f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "2D implicit-Euler upwind conv-diff 1024x1024, dt 1e-3, |v|=50 rotating 1.2 deg/step, "
+                               "p=64, source 1, u0=0, tol 1e-10", "steps": args.c4_steps, "train_steps": args.c4_train,
+                   "net": "4 layers 4098-512-512-512-2048 bf16/FP32-accumulate, Adam", "epochs": args.c4_epochs},
+        "eval_steps": len(ev),
+        "solve_ms_prev": mean("prev_ms", ev), "solve_ms_learned": mean("learn_ms", ev),
+        "inner_iters_prev": mean("prev_inner", ev), "inner_iters_learned": mean("learn_inner", ev),
+        "judge_resid_prev_median": float(np.median([r["r_prev"] for r in ev])) if ev else None,
+        "judge_resid_learned_median": float(np.median([r["r_learn"] for r in ev])) if ev else None,
+        "learned_chosen": sum(bool(r["learned"]) for r in ev),
+        "guess_ms": mean("guess_ms", ev), "features_ms": mean("features_ms", recs),
+        "factor_ms": mean("factor_ms", recs), "train_s": out["train_s"],
+        "loss_first_last": [out["loss"][0], out["loss"][-1]] if out["loss"] else None,
+        "max_relres": max(r["relres"] for r in recs), "wall_s": wall,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +230,9 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-6, help="reduced-solve tolerance, timed mode")
     ap.add_argument("--inner-tol-f64", type=float, default=1e-9, help="reduced-solve tolerance, FP64 mode")
     ap.add_argument("--graph-steps", type=int, default=2, help="extra steps timed with the factor graph")
+    ap.add_argument("--c4-steps", type=int, default=300)
+    ap.add_argument("--c4-train", type=int, default=200)
+    ap.add_argument("--c4-epochs", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -187,6 +240,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.config == "c4":
+        run_c4(args)
+        return
     log(f"building workload {args.config}")
     d = build_workload(args.config)
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")

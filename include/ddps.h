@@ -233,6 +233,93 @@ int ddps_timing_enable(ddps_handle h, int32_t kind, int32_t on);
 int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms, double* flops,
                      double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess of the reduced solve.
+ *
+ * The method leaves the starting vector of the inner Krylov solve of step
+ * 6.3 free (Figure 2).  Over a sequence of related systems (time steps of
+ * the loop of Section 1) a small network predicts it per interface from the
+ * previous step's reduced solution z^prev and its reduced residual
+ * r = g^ - G^ z^prev.  The reduced vector is p-1 interfaces of 2t entries
+ * (interface j: the last t rows of block j, then the first t rows of block
+ * j+1); one network row maps [r_j / s_j, z^prev_j / q_j, cos, sin]
+ * (s_j = max |r_j|, q_j = max |z^prev_j|; d_in >= 4t+2 floats, zero padded)
+ * to the correction (z^_j - z^prev_j) / s_j (2t floats).  The caller judges
+ * candidates with ddps_reduced_residual and passes the winner to
+ * ddps_set_guess.  Reduced vectors are device double[m*k], one column of m
+ * entries per right-hand side (k <= max_rhs).
+ * ------------------------------------------------------------------------ */
+
+/* Steps 6.1-6.2 for k columns y (device, double[n*k]): ghat = (D~^{-1} y)
+ * on the index set c, zero elsewhere.  Requires a factored handle
+ * (DDPS_E_STATE otherwise). */
+int ddps_reduced_rhs(ddps_handle h, int32_t k, const double* y, double* ghat);
+
+/* Restriction to the reduced layout: z = x on the index set c, zero
+ * elsewhere, for k columns x (device, double[n*k]); z is device double[m*k].
+ * With exact coupling (drop_delta 0) the reduced solution of a right-hand
+ * side f is the restriction of the solution of Ax = f. */
+int ddps_reduced_restrict(ddps_handle h, int32_t k, const double* x, double* z);
+
+/* Judge of a candidate guess: res (host, double[k]) receives
+ * ||ghat - G^ z||_2 over the index set c for each column (z is masked to c
+ * first); if rvec (device, double[m*k]) is not NULL it receives the residual
+ * vector itself, zero off c.  Uses the handle's reduced work vectors, so the
+ * vectors of ddps_last_reduced are overwritten. */
+int ddps_reduced_residual(ddps_handle h, int32_t k, const double* ghat, const double* z, double* res,
+                          double* rvec);
+
+/* Network inputs of the k (p-1) interfaces from the reduced residual r of
+ * zprev (ddps_reduced_residual's rvec): X (device, float[k (p-1) * d_in],
+ * row-major, row j = interface j % (p-1) of column j / (p-1)) and the scales
+ * s_j (device, float[k (p-1)]).  zprev is masked to c.  cos_t, sin_t are the
+ * two scalar features (for example the phase of a rotating velocity).
+ * DDPS_E_ARG if d_in < 4t + 2. */
+int ddps_guess_features(ddps_handle h, int32_t k, const double* r, const double* zprev, double cos_t,
+                        double sin_t, int32_t d_in, float* X, float* scale);
+
+/* zhat0 = (zprev + s_j Y_j) on c, 0 elsewhere, from network outputs Y
+ * (device, float[k (p-1) * 2t], row-major) and the scales of
+ * ddps_guess_features; zhat0 is device double[m*k]. */
+int ddps_guess_compose(ddps_handle h, int32_t k, const double* zprev, const float* Y, const float* scale,
+                       double* zhat0);
+
+/* Training target of the network: T = (zhat - zprev on c) / s_j (device,
+ * float[k (p-1) * 2t], row-major) for a reduced solution zhat. */
+int ddps_guess_target(ddps_handle h, int32_t k, const double* zhat, const double* zprev, const float* scale,
+                      float* T);
+
+/* The network itself: 4 layers d_in -> H -> H -> H -> d_out, ReLU between
+ * layers, bf16 weights and activations on MFMA with FP32 accumulation, FP32
+ * master parameters, mean-squared-error loss, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8).  Parameters are one packed float vector
+ * [W1, b1, W2, b2, W3, b3, W4, b4], W_l row-major (fan-in x fan-out).
+ * Every call is ordered on `stream`; X, Y, T are device float, row-major,
+ * batch x d_in / d_out, 1 <= batch <= max_batch. */
+typedef struct ddps_mlp_ctx* ddps_mlp;
+
+/* Creates a network with He-uniform weights drawn from `seed` (splitmix64)
+ * and zero biases.  DDPS_E_ARG on non-positive sizes, DDPS_E_NOMEM if the
+ * device allocation fails. */
+int ddps_mlp_create(ddps_mlp* m, int32_t d_in, int32_t hidden, int32_t d_out, int32_t max_batch, uint64_t seed,
+                    void* stream);
+/* Number of floats of the packed parameter vector (-1 for NULL). */
+int64_t ddps_mlp_param_count(ddps_mlp m);
+/* Host float[param_count] in and out; set_params also resets Adam's state. */
+int ddps_mlp_set_params(ddps_mlp m, const float* host_params);
+int ddps_mlp_get_params(ddps_mlp m, float* host_params);
+/* Y = net(X).  Asynchronous on the stream. */
+int ddps_mlp_forward(ddps_mlp m, int32_t batch, const float* X, float* Y);
+/* One Adam step on mean((net(X) - T)^2) with learning rate lr > 0; loss
+ * (host, may be NULL) receives the loss before the step (synchronises). */
+int ddps_mlp_train_step(ddps_mlp m, int32_t batch, const float* X, const float* T, float lr, double* loss);
+/* Gradients of mean((net(X) - T)^2) without a step: host_grads (host,
+ * float[param_count], may be NULL) and loss (host, may be NULL). */
+int ddps_mlp_gradients(ddps_mlp m, int32_t batch, const float* X, const float* T, float* host_grads,
+                       double* loss);
+/* Releases the network; NULL is ignored. */
+void ddps_mlp_destroy(ddps_mlp m);
+
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);
 

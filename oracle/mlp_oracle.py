@@ -18,9 +18,11 @@ addition beside the method (its residual decides whether its guess is used).
 Backward pass: the chain rule written out layer by layer; Adam: Kingma & Ba
 (2015), Algorithm 1, with bias correction.  All arithmetic is float64; the
 `bf16` switch rounds the tensors the GPU keeps in bfloat16 (weights used in
-the products, the input and the stored activations) to bfloat16 with
+the products, the input, the stored activations and, in the backward pass,
+the output error dy and the pre-activation errors dz) to bfloat16 with
 round-to-nearest-even at the same points, so the two sides differ only by
-accumulation order.
+accumulation order and by where the ReLU test falls for z within rounding
+of zero.
 """
 from __future__ import annotations
 
@@ -68,16 +70,16 @@ def backward(params, cache, y, target, bf16=False):
     """Gradients of mse(y, target) with respect to every parameter."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
     a0, z1, a1, z2, a2, z3, a3 = cache
-    dy = 2.0 * (y - target) / y.size
+    dy = _r(2.0 * (y - target) / y.size, bf16)
     dW4 = a3.T @ dy
     db4 = dy.sum(axis=0)
-    dz3 = (dy @ _r(W4, bf16).T) * (z3 > 0)
+    dz3 = _r((dy @ _r(W4, bf16).T) * (z3 > 0), bf16)
     dW3 = a2.T @ dz3
     db3 = dz3.sum(axis=0)
-    dz2 = (dz3 @ _r(W3, bf16).T) * (z2 > 0)
+    dz2 = _r((dz3 @ _r(W3, bf16).T) * (z2 > 0), bf16)
     dW2 = a1.T @ dz2
     db2 = dz2.sum(axis=0)
-    dz1 = (dz2 @ _r(W2, bf16).T) * (z1 > 0)
+    dz1 = _r((dz2 @ _r(W2, bf16).T) * (z1 > 0), bf16)
     dW1 = a0.T @ dz1
     db1 = dz1.sum(axis=0)
     return [dW1, db1, dW2, db2, dW3, db3, dW4, db4]
@@ -107,3 +109,80 @@ def init_params(d_in, hidden, d_out, seed):
         out.append(rng.uniform(-lim, lim, (a, b)))
         out.append(np.zeros(b))
     return out
+
+
+# --------------------------------------------------------------------------
+# Reduced-vector plumbing of the learned guess (project definition).
+#
+# The reduced system of stage 6.3 has one unknown per column of the index set
+# c.  The guess network works interface by interface, so its vectors use the
+# candidate layout: interface j (between blocks j and j+1) owns the 2t
+# candidate columns [part[j+1] - t, part[j+1] + t) -- the last t columns of
+# block j, then the first t of block j+1 -- and a mask marks which of them
+# are in c.
+# --------------------------------------------------------------------------
+def candidate_layout(part_ptr, t, c):
+    """Candidate columns (int64[2t(p-1)]) and their mask (1.0 where in c)."""
+    part = np.asarray(part_ptr, dtype=np.int64)
+    cand = np.concatenate([np.arange(part[j + 1] - t, part[j + 1] + t, dtype=np.int64)
+                           for j in range(len(part) - 2)]) if len(part) > 2 else np.zeros(0, np.int64)
+    mask = np.isin(cand, np.asarray(c, dtype=np.int64)).astype(np.float64)
+    return cand, mask
+
+
+def to_candidates(v_c, c, cand):
+    """A vector on c (compressed, in the order of c) spread onto the
+    candidate layout, zero off c."""
+    pos = {int(col): i for i, col in enumerate(c)}
+    out = np.zeros(len(cand))
+    for q, col in enumerate(cand):
+        i = pos.get(int(col))
+        if i is not None:
+            out[q] = v_c[i]
+    return out
+
+
+def guess_features(r, zprev, mask, t, cos_t, sin_t, d_in):
+    """Rows [r_j / s_j, (z^prev_j on c) / q_j, cos, sin, 0...] with
+    s_j = max |r_j| and q_j = max |z^prev_j on c| (1 where zero); r is the
+    reduced residual g^ - G^ z^prev.  Returns (X float32[(p-1) x d_in],
+    s float32[p-1])."""
+    w = 2 * t
+    nif = len(r) // w
+    X = np.zeros((nif, d_in), dtype=np.float32)
+    s = np.zeros(nif, dtype=np.float32)
+
+    def absmax(v):
+        a = np.max(np.abs(v))
+        return a if a > 1e-300 else 1.0
+
+    for j in range(nif):
+        rj = r[j * w:(j + 1) * w]
+        z = zprev[j * w:(j + 1) * w] * mask[j * w:(j + 1) * w]
+        sj, qj = absmax(rj), absmax(z)
+        X[j, :w] = (rj / sj).astype(np.float32)
+        X[j, w:2 * w] = (z / qj).astype(np.float32)
+        X[j, 2 * w] = np.float32(cos_t)
+        X[j, 2 * w + 1] = np.float32(sin_t)
+        s[j] = np.float32(sj)
+    return X, s
+
+
+def guess_compose(zprev, Y, s, mask, t):
+    """Initial guess z^0 = (z^prev + s_j Y_j) on c, 0 off c."""
+    w = 2 * t
+    out = np.zeros(len(zprev))
+    for j in range(len(s)):
+        sl = slice(j * w, (j + 1) * w)
+        out[sl] = (zprev[sl] + np.float64(s[j]) * Y[j].astype(np.float64)) * mask[sl]
+    return out
+
+
+def guess_target(zhat, zprev, s, mask, t):
+    """Training target (z^_j - z^prev_j on c) / s_j, float32[(p-1) x 2t]."""
+    w = 2 * t
+    T = np.zeros((len(s), w), dtype=np.float32)
+    for j in range(len(s)):
+        sl = slice(j * w, (j + 1) * w)
+        T[j] = ((zhat[sl] - zprev[sl] * mask[sl]) / np.float64(s[j])).astype(np.float32)
+    return T

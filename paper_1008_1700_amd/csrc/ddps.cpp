@@ -18,6 +18,7 @@
 // blocks advance together and one launch fills the GPU.
 #include "../../include/ddps.h"
 #include "ddps_internal.h"
+#include "ddps_mlp_internal.h"
 
 #include <algorithm>
 #include <array>
@@ -865,7 +866,7 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
                int use_guess, std::vector<int>& iters, int* breakdown) {
   const int R = h->R;
   hipStream_t s = h->stream;
-  vec_to_padded(h->Np, R, h->p, h->d_blk, y, ldy, h->d_ypad, s);
+  vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, ldy, h->d_ypad, s);
   int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
   if (rc) return rc;
   rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
@@ -881,7 +882,7 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
   }
   rc = run_schedule(h, h->sch_retr, R, h->m, h->Np, TK_RETR);
   if (rc) return rc;
-  vec_from_padded(h->Np, R, h->p, h->d_blk, h->d_vpad, z, ldz, s);
+  vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_vpad, z, ldz, s);
   HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
@@ -1528,12 +1529,12 @@ int ddps_block_solve(ddps_handle h, int32_t k, const double* y, double* g) {
   if (!h || !y || !g || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
   if (!h->factored) return DDPS_E_STATE;
   const int R = h->R;
-  vec_to_padded(h->Np, R, h->p, h->d_blk, y, h->n, h->d_ypad, h->stream);
+  vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, h->n, h->d_ypad, h->stream);
   int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
   if (rc) return rc;
   rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
   if (rc) return rc;
-  vec_from_padded(h->Np, R, h->p, h->d_blk, h->d_ypad, g, h->n, h->stream);
+  vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_ypad, g, h->n, h->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
   return DDPS_OK;
@@ -1548,6 +1549,99 @@ int ddps_reduced_matvec(ddps_handle h, int32_t k, const double* x, double* v) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(v, h->d_v, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  return DDPS_OK;
+}
+
+
+// ---------------------------------------------------------------- learned guess
+int ddps_reduced_rhs(ddps_handle h, int32_t k, const double* y, double* ghat) {
+  if (!h || !y || !ghat || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  if (h->m == 0) return DDPS_OK;
+  const int R = h->R;
+  hipStream_t s = h->stream;
+  vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, h->n, h->d_ypad, s);
+  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  if (rc) return rc;
+  vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_r, s);
+  HIPCHK(hipMemcpyAsync(ghat, h->d_r, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return DDPS_OK;
+}
+
+int ddps_reduced_restrict(ddps_handle h, int32_t k, const double* x, double* z) {
+  if (!h || !x || !z || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (h->m == 0) return DDPS_OK;
+  const int R = h->R;
+  hipStream_t s = h->stream;
+  vec_to_padded(h->Np, R, k, h->p, h->d_blk, x, h->n, h->d_ypad, s);
+  vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_r, s);
+  HIPCHK(hipMemcpyAsync(z, h->d_r, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return DDPS_OK;
+}
+
+int ddps_reduced_residual(ddps_handle h, int32_t k, const double* ghat, const double* z, double* res, double* rvec) {
+  if (!h || !ghat || !z || !res || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (!h->factored) return DDPS_E_STATE;
+  const int R = h->R;
+  const int64_t m = h->m;
+  if (m == 0) {
+    for (int j = 0; j < k; ++j) res[j] = 0.0;
+    return DDPS_OK;
+  }
+  hipStream_t s = h->stream;
+  fill_f64(h->d_zh, m * R, 0.0, s);
+  fill_f64(h->d_r, m * R, 0.0, s);
+  HIPCHK(hipMemcpyAsync(h->d_zh, z, sizeof(double) * m * k, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_r, ghat, sizeof(double) * m * k, hipMemcpyDeviceToDevice, s));
+  vec_apply_mask(m, R, h->d_mask, h->d_zh, s);
+  run_launch(h, h->l_zv, R, m, m, nullptr, nullptr, nullptr, TK_RSPMV);
+  Coef3 cf{};
+  for (int j = 0; j < R; ++j) {
+    cf.a[j] = 1.0;
+    cf.b[j] = -1.0;
+  }
+  lincomb(R, m, cf, h->d_r, h->d_v, nullptr, h->d_r, s);
+  vec_apply_mask(m, R, h->d_mask, h->d_r, s);
+  if (rvec) HIPCHK(hipMemcpyAsync(rvec, h->d_r, sizeof(double) * m * k, hipMemcpyDeviceToDevice, s));
+  std::vector<double> d0, d1;
+  int rc = dots(h, m, h->d_r, h->d_r, nullptr, nullptr, d0, d1);
+  if (rc) return rc;
+  for (int j = 0; j < k; ++j) res[j] = std::sqrt(d0[j]);
+  return DDPS_OK;
+}
+
+int ddps_guess_features(ddps_handle h, int32_t k, const double* r, const double* zprev, double cos_t,
+                        double sin_t, int32_t d_in, float* X, float* scale) {
+  if (!h || !r || !zprev || !X || !scale || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (d_in < 4 * h->t + 2) return DDPS_E_ARG;
+  if (h->m == 0) return DDPS_OK;
+  const int nif = h->p - 1;
+  guess_features(nif, k, 2 * h->t, d_in, r, zprev, h->d_mask, cos_t, sin_t, X, scale, h->stream);
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
+int ddps_guess_compose(ddps_handle h, int32_t k, const double* zprev, const float* Y, const float* scale,
+                       double* zhat0) {
+  if (!h || !zprev || !Y || !scale || !zhat0 || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (h->m == 0) return DDPS_OK;
+  guess_compose(h->m * k, h->m, 2 * h->t, zprev, Y, scale, h->d_mask, zhat0, h->stream);
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
+int ddps_guess_target(ddps_handle h, int32_t k, const double* zhat, const double* zprev, const float* scale,
+                      float* T) {
+  if (!h || !zhat || !zprev || !scale || !T || k < 1 || k > h->opt.max_rhs) return DDPS_E_ARG;
+  if (h->m == 0) return DDPS_OK;
+  guess_target(h->m * k, h->m, 2 * h->t, zhat, zprev, scale, h->d_mask, T, h->stream);
+  HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
 

@@ -152,9 +152,11 @@ void fill_f64(double* ptr, int64_t count, double v, hipStream_t s);
 void fill_f32(float* ptr, int64_t count, float v, hipStream_t s);
 void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipStream_t s);
 
-void vec_to_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* y, int64_t ldy,
+// y holds k <= R columns (leading dimension ldy); the padded vector has R,
+// and its columns k..R-1 are zeroed.  from_padded writes k columns of y.
+void vec_to_padded(int64_t Np, int R, int k, int p, const BlockInfo* blocks, const double* y, int64_t ldy,
                    double* yp, hipStream_t s);
-void vec_from_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* yp, double* y,
+void vec_from_padded(int64_t Np, int k, int p, const BlockInfo* blocks, const double* yp, double* y,
                      int64_t ldy, hipStream_t s);
 void vec_gather_reduced(int64_t m, int R, const int64_t* rrow, const double* mask, const double* gp,
                         int64_t Np, double* gh, hipStream_t s);

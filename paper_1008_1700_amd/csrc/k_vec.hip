@@ -78,25 +78,27 @@ __device__ __forceinline__ int find_voff(const BlockInfo* __restrict__ b, int p,
   return lo;
 }
 
-__global__ void k_to_padded(int64_t Np, int R, int p, const BlockInfo* __restrict__ blocks,
+// R columns of the padded vector; only the first k exist in y, the rest are zeroed
+__global__ void k_to_padded(int64_t Np, int R, int k, int p, const BlockInfo* __restrict__ blocks,
                             const double* __restrict__ y, int64_t ldy, double* __restrict__ yp) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Np;
        q += (int64_t)gridDim.x * blockDim.x) {
     const BlockInfo B = blocks[find_voff(blocks, p, q)];
     const int64_t lr = q - B.voff;
     for (int j = 0; j < R; ++j)
-      yp[q + j * Np] = lr < B.pad ? 0.0 : y[B.s + (lr - B.pad) + j * ldy];
+      yp[q + j * Np] = (lr < B.pad || j >= k) ? 0.0 : y[B.s + (lr - B.pad) + j * ldy];
   }
 }
 
-__global__ void k_from_padded(int64_t Np, int R, int p, const BlockInfo* __restrict__ blocks,
+// writes the first k columns of y
+__global__ void k_from_padded(int64_t Np, int k, int p, const BlockInfo* __restrict__ blocks,
                               const double* __restrict__ yp, double* __restrict__ y, int64_t ldy) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Np;
        q += (int64_t)gridDim.x * blockDim.x) {
     const BlockInfo B = blocks[find_voff(blocks, p, q)];
     const int64_t lr = q - B.voff;
     if (lr >= B.pad)
-      for (int j = 0; j < R; ++j) y[B.s + (lr - B.pad) + j * ldy] = yp[q + j * Np];
+      for (int j = 0; j < k; ++j) y[B.s + (lr - B.pad) + j * ldy] = yp[q + j * Np];
   }
 }
 
@@ -513,13 +515,13 @@ static inline unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kVecGrid));
 }
 
-void vec_to_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* y, int64_t ldy,
+void vec_to_padded(int64_t Np, int R, int k, int p, const BlockInfo* blocks, const double* y, int64_t ldy,
                    double* yp, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_padded, dim3(grid_for(Np)), dim3(256), 0, s, Np, R, p, blocks, y, ldy, yp);
+  hipLaunchKernelGGL(k_to_padded, dim3(grid_for(Np)), dim3(256), 0, s, Np, R, k, p, blocks, y, ldy, yp);
 }
-void vec_from_padded(int64_t Np, int R, int p, const BlockInfo* blocks, const double* yp, double* y,
+void vec_from_padded(int64_t Np, int k, int p, const BlockInfo* blocks, const double* yp, double* y,
                      int64_t ldy, hipStream_t s) {
-  hipLaunchKernelGGL(k_from_padded, dim3(grid_for(Np)), dim3(256), 0, s, Np, R, p, blocks, yp, y, ldy);
+  hipLaunchKernelGGL(k_from_padded, dim3(grid_for(Np)), dim3(256), 0, s, Np, k, p, blocks, yp, y, ldy);
 }
 void vec_gather_reduced(int64_t m, int R, const int64_t* rrow, const double* mask, const double* gp,
                         int64_t Np, double* gh, hipStream_t s) {

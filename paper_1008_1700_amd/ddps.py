@@ -96,6 +96,20 @@ _SIGS = {
     "ddps_timing_enable": (_I32, [_P, _I32, _I32]),
     "ddps_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D),
                                 ctypes.POINTER(_D)]),
+    "ddps_reduced_rhs": (_I32, [_P, _I32, _P, _P]),
+    "ddps_reduced_restrict": (_I32, [_P, _I32, _P, _P]),
+    "ddps_reduced_residual": (_I32, [_P, _I32, _P, _P, ctypes.POINTER(_D), _P]),
+    "ddps_guess_features": (_I32, [_P, _I32, _P, _P, _D, _D, _I32, _P, _P]),
+    "ddps_guess_compose": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "ddps_guess_target": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "ddps_mlp_create": (_I32, [ctypes.POINTER(_P), _I32, _I32, _I32, _I32, ctypes.c_uint64, _P]),
+    "ddps_mlp_param_count": (_I64, [_P]),
+    "ddps_mlp_set_params": (_I32, [_P, _P]),
+    "ddps_mlp_get_params": (_I32, [_P, _P]),
+    "ddps_mlp_forward": (_I32, [_P, _I32, _P, _P]),
+    "ddps_mlp_train_step": (_I32, [_P, _I32, _P, _P, ctypes.c_float, ctypes.POINTER(_D)]),
+    "ddps_mlp_gradients": (_I32, [_P, _I32, _P, _P, _P, ctypes.POINTER(_D)]),
+    "ddps_mlp_destroy": (None, [_P]),
     "ddps_memory": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "ddps_destroy": (None, [_P]),
     "ddps_status_string": (ctypes.c_char_p, [_I32]),
@@ -267,6 +281,80 @@ def ddps_timing_read(h, kind):
     _chk(lib().ddps_timing_read(h, TIMING_KINDS.get(kind, kind), ctypes.byref(n), ctypes.byref(ms),
                                 ctypes.byref(fl), ctypes.byref(by)), "ddps_timing_read")
     return dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
+
+
+def ddps_reduced_rhs(h, k, y, ghat):
+    _chk(lib().ddps_reduced_rhs(h, int(k), _ptr(y), _ptr(ghat)), "ddps_reduced_rhs")
+
+
+def ddps_reduced_restrict(h, k, x, z):
+    _chk(lib().ddps_reduced_restrict(h, int(k), _ptr(x), _ptr(z)), "ddps_reduced_restrict")
+
+
+def ddps_reduced_residual(h, k, ghat, z, rvec=None):
+    res = (ctypes.c_double * max(1, k))()
+    _chk(lib().ddps_reduced_residual(h, int(k), _ptr(ghat), _ptr(z), res, _ptr(rvec)), "ddps_reduced_residual")
+    return [res[j] for j in range(k)]
+
+
+def ddps_guess_features(h, k, r, zprev, cos_t, sin_t, d_in, X, scale):
+    _chk(lib().ddps_guess_features(h, int(k), _ptr(r), _ptr(zprev), float(cos_t), float(sin_t), int(d_in),
+                                   _ptr(X), _ptr(scale)), "ddps_guess_features")
+
+
+def ddps_guess_compose(h, k, zprev, Y, scale, zhat0):
+    _chk(lib().ddps_guess_compose(h, int(k), _ptr(zprev), _ptr(Y), _ptr(scale), _ptr(zhat0)),
+         "ddps_guess_compose")
+
+
+def ddps_guess_target(h, k, zhat, zprev, scale, T):
+    _chk(lib().ddps_guess_target(h, int(k), _ptr(zhat), _ptr(zprev), _ptr(scale), _ptr(T)), "ddps_guess_target")
+
+
+def ddps_mlp_create(d_in, hidden, d_out, max_batch, seed=0, stream=None):
+    m = ctypes.c_void_p()
+    _chk(lib().ddps_mlp_create(ctypes.byref(m), int(d_in), int(hidden), int(d_out), int(max_batch),
+                               ctypes.c_uint64(seed), ctypes.c_void_p(stream or 0)), "ddps_mlp_create")
+    return m
+
+
+def ddps_mlp_param_count(m):
+    return int(lib().ddps_mlp_param_count(m))
+
+
+def ddps_mlp_set_params(m, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _chk(lib().ddps_mlp_set_params(m, a.ctypes.data_as(ctypes.c_void_p)), "ddps_mlp_set_params")
+
+
+def ddps_mlp_get_params(m):
+    a = np.empty(ddps_mlp_param_count(m), dtype=np.float32)
+    _chk(lib().ddps_mlp_get_params(m, a.ctypes.data_as(ctypes.c_void_p)), "ddps_mlp_get_params")
+    return a
+
+
+def ddps_mlp_forward(m, batch, X, Y):
+    _chk(lib().ddps_mlp_forward(m, int(batch), _ptr(X), _ptr(Y)), "ddps_mlp_forward")
+
+
+def ddps_mlp_train_step(m, batch, X, T, lr, want_loss=True):
+    loss = ctypes.c_double()
+    _chk(lib().ddps_mlp_train_step(m, int(batch), _ptr(X), _ptr(T), ctypes.c_float(lr),
+                                   ctypes.byref(loss) if want_loss else None), "ddps_mlp_train_step")
+    return loss.value if want_loss else None
+
+
+def ddps_mlp_gradients(m, batch, X, T):
+    g = np.empty(ddps_mlp_param_count(m), dtype=np.float32)
+    loss = ctypes.c_double()
+    _chk(lib().ddps_mlp_gradients(m, int(batch), _ptr(X), _ptr(T), g.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(loss)), "ddps_mlp_gradients")
+    return g, loss.value
+
+
+def ddps_mlp_destroy(m):
+    if m:
+        lib().ddps_mlp_destroy(m)
 
 
 def ddps_memory(h):

@@ -70,3 +70,72 @@ def test_round_bf16_known_values():
     # 1e-40 is a float32 subnormal: rounding keeps it a (tiny) subnormal
     assert np.array_equal(got[:6], exp[:6])
     assert abs(got[6]) < 1e-39
+
+
+def test_bf16_switch_is_exact_on_representable_values():
+    # Small-integer weights and inputs keep every intermediate an integer
+    # below 256 (a bf16 value) and the batch*d_out = 8 divisor a power of two,
+    # so the bf16 rounding points must not change anything.
+    rng = np.random.default_rng(7)
+    p = []
+    for a, b in [(3, 4), (4, 4), (4, 4), (4, 2)]:
+        p.append(rng.integers(-1, 2, (a, b)).astype(np.float64))
+        p.append(rng.integers(-1, 2, b).astype(np.float64))
+    x = rng.integers(-2, 3, (4, 3)).astype(np.float64)
+    t = rng.integers(-2, 3, (4, 2)).astype(np.float64)
+    y0, c0 = M.forward(p, x, bf16=False)
+    y1, c1 = M.forward(p, x, bf16=True)
+    assert np.array_equal(y0, y1)
+    g0 = M.backward(p, c0, y0, t, bf16=False)
+    g1 = M.backward(p, c1, y1, t, bf16=True)
+    for a, b in zip(g0, g1):
+        assert np.array_equal(a, b)
+
+
+def test_bf16_switch_rounds_the_backward_signal():
+    # 1x1 identity layers and x = 1 give a3 = 1, so dW4 = a3^T dy = dy; with
+    # y - t = (1 + 2^-10) / 2 and N = 1, dy = 1 + 2^-10, which is not a bf16
+    # value and must round to 1.
+    p = [np.eye(1), np.zeros(1), np.eye(1), np.zeros(1), np.eye(1), np.zeros(1), np.eye(1), np.zeros(1)]
+    x = np.array([[1.0]])
+    y, cache = M.forward(p, x, bf16=True)
+    tgt = y - (1.0 + 2.0 ** -10) / 2.0
+    g = M.backward(p, cache, y, tgt, bf16=True)
+    assert g[6][0, 0] == 1.0            # 1 + 2^-10 rounds to 1 in bf16
+    g64 = M.backward(p, cache, y, tgt, bf16=False)
+    assert g64[6][0, 0] == 1.0 + 2.0 ** -10
+
+
+def test_candidate_layout_and_spread():
+    part = [0, 10, 22, 30]
+    cand, mask = M.candidate_layout(part, 3, [8, 9, 10, 20, 23])
+    assert list(cand) == [7, 8, 9, 10, 11, 12, 19, 20, 21, 22, 23, 24]
+    assert list(mask) == [0, 1, 1, 1, 0, 0, 0, 1, 0, 0, 1, 0]
+    v = M.to_candidates(np.array([1.0, 2.0, 3.0, 4.0, 5.0]), [8, 9, 10, 20, 23], cand)
+    assert list(v) == [0, 1, 2, 3, 0, 0, 0, 4, 0, 0, 5, 0]
+
+
+def test_guess_features_compose_target_round_trip():
+    # compose(target(z)) returns z on c (up to the float32 rounding of T), the
+    # r and z^prev parts of each feature row have max-norm 1, and a zero r
+    # gives scale 1.
+    rng = np.random.default_rng(11)
+    t = 4
+    w = 2 * t
+    nif = 3
+    mask = (rng.uniform(size=nif * w) > 0.3).astype(np.float64)
+    gh = rng.standard_normal(nif * w) * mask * 10.0
+    gh[w:2 * w] = 0.0
+    zp = rng.standard_normal(nif * w)
+    zh = rng.standard_normal(nif * w) * mask
+    X, s = M.guess_features(gh, zp, mask, t, 0.5, -0.25, 4 * t + 5)
+    assert X.shape == (nif, 4 * t + 5) and np.all(X[:, 4 * t + 2:] == 0)
+    assert np.isclose(np.max(np.abs(X[0, :w])), 1.0) and s[1] == 1.0
+    assert np.all(X[:, 2 * w] == np.float32(0.5)) and np.all(X[:, 2 * w + 1] == np.float32(-0.25))
+    zm = zp * mask
+    assert np.allclose(X[2, w:2 * w], zm[2 * w:] / np.max(np.abs(zm[2 * w:])), rtol=1e-6)
+    assert np.isclose(np.max(np.abs(X[0, w:2 * w])), 1.0)
+    T = M.guess_target(zh, zp, s, mask, t)
+    z0 = M.guess_compose(zp, T, s, mask, t)
+    assert np.allclose(z0, zh, rtol=1e-6, atol=1e-6 * np.max(np.abs(zh)))
+    assert np.all(z0[mask == 0] == 0)

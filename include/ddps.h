@@ -121,8 +121,10 @@ int ddps_setup(ddps_handle* h, int64_t n, int32_t p, const int64_t* part_ptr,
  * pivoting, and the spikes G_i = A_ii^{-1} R~_i(:, c_i) for all blocks, in
  * the factor dtype.  The reduced matrix G^ = I(c,c) + G(c,c) of Figure 2,
  * step 6.2, is the set of spike rows at c; it is used in place.
- * Errors: DDPS_E_SINGULAR (info of the next ddps_solve reports the block and
- * row; also readable with ddps_last_singular), DDPS_E_HIP. */
+ * Errors: DDPS_E_SINGULAR when a pivot |u_kk| <= 1e3 eps max_j |a_kj| (the
+ * largest in-block entry of that row, eps of the factor dtype) or is not
+ * finite (info of the next ddps_solve reports the block and row; also
+ * readable with ddps_last_singular), DDPS_E_HIP. */
 int ddps_factor(ddps_handle h);
 
 /* Replaces the values of A (same sparsity pattern as at setup; device,

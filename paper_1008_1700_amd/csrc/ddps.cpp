@@ -93,9 +93,9 @@ struct ddps_ctx {
   double* d_val = nullptr;
   BlockInfo* d_blk = nullptr;
   void *d_tiles = nullptr, *d_spikes = nullptr, *d_scratch = nullptr;
-  unsigned long long *d_colnorm = nullptr, *d_blknorm = nullptr, *d_bad = nullptr, *d_band = nullptr;
+  unsigned long long *d_colnorm = nullptr, *d_bad = nullptr, *d_band = nullptr;
   unsigned int* d_flags = nullptr;
-  double* d_thresh = nullptr;
+  double* d_thresh = nullptr;   // per padded row: pivot threshold
   double* d_mask = nullptr;
   int64_t *d_c = nullptr, *d_rrow = nullptr;
   GemmProb* d_gemm = nullptr;
@@ -318,9 +318,9 @@ struct ScheduleBuilder {
   void add_copy(const void* src, int lds, void* dst, int ldd, int M, int N) {
     add_gemm(nullptr, 0, nullptr, 0, src, lds, dst, ldd, M, N, 0, 0);
   }
-  void add_panel(void* D, int ld, int block, int64_t row0) {
+  void add_panel(void* D, int ld, int block, int64_t row0, int64_t vrow0) {
     PanelProb P{};
-    P.D = D; P.ld = ld; P.block = block; P.row0 = row0;
+    P.D = D; P.ld = ld; P.block = block; P.row0 = row0; P.vrow0 = vrow0;
     panel.push_back(P);
     nwg += 1;
     flops += 2.0 / 3.0 * 64 * 64 * 64 * 2.0;
@@ -387,7 +387,8 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       sb.begin(LK_PANEL);
       for (int i : act) {
         const BlockInfo& B = h->blk[i];
-        sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64);
+        sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64,
+                     B.voff + (int64_t)k * t + j64);
       }
       sb.end(S);
       if (rest <= 0) continue;
@@ -1064,7 +1065,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   int rc;
   if ((rc = h->alloc(h->d_part, p + 1)) || (rc = h->alloc(h->d_rowptr, n + 1)) || (rc = h->alloc(h->d_col, nnz)) ||
       (rc = h->alloc(h->d_val, nnz)) || (rc = h->alloc(h->d_band, 1)) || (rc = h->alloc(h->d_flags, 1)) ||
-      (rc = h->alloc(h->d_blknorm, p)) || (rc = h->alloc(h->d_thresh, p)) || (rc = h->alloc(h->d_bad, 1)))
+      (rc = h->alloc(h->d_bad, 1)))
     return fail(rc);
   hipStream_t s = h->stream;
   if (hipMemcpyAsync(h->d_part, part_ptr, sizeof(int64_t) * (p + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -1073,12 +1074,11 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
       hipMemcpyAsync(h->d_val, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(DDPS_E_HIP);
   fill_u64(h->d_band, 1, 0ull, s);
-  fill_u64(h->d_blknorm, p, 0ull, s);
   {
     unsigned int* f = h->d_flags;
     fill_f32((float*)f, 1, 0.f, s);
   }
-  setup_scan(n, p, h->d_part, h->d_rowptr, h->d_col, h->d_val, nnz, h->d_band, h->d_flags, h->d_blknorm, s);
+  setup_scan(n, p, h->d_part, h->d_rowptr, h->d_col, h->d_val, nnz, h->d_band, h->d_flags, s);
   unsigned long long band = 0;
   unsigned int flags = 0;
   if (hipMemcpyAsync(&band, h->d_band, sizeof(band), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1124,7 +1124,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   need += (size_t)h->nspike * h->elt;
   need += (size_t)p * h->scr_per_block * h->elt;
   need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
-  need += (size_t)h->Np * R * 8 * 2;
+  need += (size_t)h->Np * R * 8 * 2 + (size_t)h->Np * 8;
   need += (size_t)m * R * 8 * 9;
   need += (size_t)n * R * 8 * 10;
   need += (size_t)Wmax * R * 4 * 8;
@@ -1144,7 +1144,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->d_scratch = vp;
   if ((rc = h->alloc(h->d_colnorm, (int64_t)p * 2 * t)) || (rc = h->alloc(h->d_mask, std::max<int64_t>(m, 1))) ||
       (rc = h->alloc(h->d_c, std::max<int64_t>(m, 1))) || (rc = h->alloc(h->d_rrow, std::max<int64_t>(m, 1))) ||
-      (rc = h->alloc(h->d_blk, p)) || (rc = h->alloc(h->d_ypad, h->Np * R)) || (rc = h->alloc(h->d_vpad, h->Np * R)))
+      (rc = h->alloc(h->d_blk, p)) || (rc = h->alloc(h->d_ypad, h->Np * R)) || (rc = h->alloc(h->d_vpad, h->Np * R)) ||
+      (rc = h->alloc(h->d_thresh, h->Np)))
     return fail(rc);
   const int64_t mR = std::max<int64_t>(m, 1) * R;
   if ((rc = h->alloc(h->d_gh, mR)) || (rc = h->alloc(h->d_zh, mR)) || (rc = h->alloc(h->d_r, mR)) ||
@@ -1187,7 +1188,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (hipMemcpyAsync(h->d_blk, h->blk.data(), sizeof(BlockInfo) * p, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(DDPS_E_HIP);
   const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
-  setup_thresh(p, eps, h->d_blknorm, h->d_thresh, s);
+  setup_row_thresh(n, p, h->Np, h->d_part, h->d_blk, h->d_rowptr, h->d_col, h->d_val, eps, h->d_thresh, s);
   // execution resources and schedules
   if (hipStreamCreateWithFlags(&h->fstream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
@@ -1261,12 +1262,11 @@ int ddps_refactor_values(ddps_handle h, const double* val) {
   if (!h || !val) return DDPS_E_ARG;
   HIPCHK(hipMemcpyAsync(h->d_val, val, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
   fill_u64(h->d_band, 1, 0ull, h->stream);
-  fill_u64(h->d_blknorm, h->p, 0ull, h->stream);
   fill_f32((float*)h->d_flags, 1, 0.f, h->stream);
-  setup_scan(h->n, h->p, h->d_part, h->d_rowptr, h->d_col, h->d_val, h->nnz, h->d_band, h->d_flags, h->d_blknorm,
-             h->stream);
+  setup_scan(h->n, h->p, h->d_part, h->d_rowptr, h->d_col, h->d_val, h->nnz, h->d_band, h->d_flags, h->stream);
   const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
-  setup_thresh(h->p, eps, h->d_blknorm, h->d_thresh, h->stream);
+  setup_row_thresh(h->n, h->p, h->Np, h->d_part, h->d_blk, h->d_rowptr, h->d_col, h->d_val, eps, h->d_thresh,
+                   h->stream);
   unsigned int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

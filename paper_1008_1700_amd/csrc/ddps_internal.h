@@ -51,8 +51,9 @@ struct GemmProb {
 struct PanelProb {
   void* D;        // first element of the 64 x 64 sub-tile
   int32_t ld;
-  int32_t block;  // block index (for pivot threshold and error report)
+  int32_t block;  // block index (error report)
   int64_t row0;   // global row of the sub-tile's first row (may be < block start: padding)
+  int64_t vrow0;  // the same row in the padded layout (indexes the per-row pivot thresholds)
 };
 
 // ---------------------------------------------------------------- GEMV
@@ -140,14 +141,17 @@ void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
 
 void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
-                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags,
-                unsigned long long* blknorm, hipStream_t s);
+                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags, hipStream_t s);
 void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, const BlockInfo* blocks,
                    const int64_t* row_ptr, const int32_t* col, const double* val, void* tiles,
                    void* spikes, unsigned long long* colnorm, unsigned int* flags, hipStream_t s);
 void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
                 const unsigned long long* colnorm, double* mask, void* spikes, hipStream_t s);
-void setup_thresh(int p, double eps, const unsigned long long* blknorm, double* thresh, hipStream_t s);
+// Pivot thresholds per row of the padded layout (Np entries): 1e3 eps times the
+// row's largest in-block magnitude; 0 on padding rows.
+void setup_row_thresh(int64_t n, int p, int64_t Np, const int64_t* part, const BlockInfo* blocks,
+                      const int64_t* row_ptr, const int32_t* col, const double* val, double eps, double* thresh,
+                      hipStream_t s);
 void fill_f64(double* ptr, int64_t count, double v, hipStream_t s);
 void fill_f32(float* ptr, int64_t count, float v, hipStream_t s);
 void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipStream_t s);

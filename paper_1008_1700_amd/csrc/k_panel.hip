@@ -20,9 +20,10 @@
 // right; the X sums read X(r,l) for l > j, final since columns go right to
 // left; both read the factors from LDS, never from other lanes).
 //
-// Pivot check: a pivot u_kk with |u_kk| <= thresh[block] (or not finite)
-// records (block, global row) in *bad through an atomic minimum, so the
-// first bad pivot in (block, row) order is reported.
+// Pivot check: a pivot u_kk with |u_kk| <= thresh[row] (the row's own
+// threshold in the padded layout) or not finite records (block, global row)
+// in *bad through an atomic minimum, so the first bad pivot in (block, row)
+// order is reported.
 #include "ddps_internal.h"
 
 namespace ddps {
@@ -40,7 +41,6 @@ __global__ __launch_bounds__(64) void k_panel(const PanelProb* __restrict__ prob
   T a[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) a[c] = D[(int64_t)c * P.ld + r];
-  const double th = thresh[P.block];
 
   // Every loop is fully unrolled: register indices are compile-time
   // constants and the triangular loop bounds prune at compile time.
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void k_panel(const PanelProb* __restrict__ prob
     const T piv = Ur[k][k];
     if (r == 0) {
       const double av = fabs((double)piv);
-      if (!(av > th) || !(av <= 1.7e308)) {
+      if (!(av > thresh[P.vrow0 + k]) || !(av <= 1.7e308)) {
         const unsigned long long key =
             ((unsigned long long)P.block << 40) | (unsigned long long)(P.row0 + k);
         atomicMin(bad, key);

@@ -18,33 +18,24 @@ __device__ __forceinline__ int find_block(const int64_t* __restrict__ part, int 
   return lo;
 }
 
-// One thread per row; band, flags and per-block norms are reduced inside the
-// workgroup first (rows of a workgroup nearly always share one block), so
-// only a few atomics per workgroup reach memory.
-__global__ __launch_bounds__(256) void k_scan_rows(int64_t n, int p, const int64_t* __restrict__ part,
-                                                   const int64_t* __restrict__ row_ptr,
+// One thread per row; band and flags are reduced inside the workgroup first,
+// so only one atomic per workgroup reaches memory.
+__global__ __launch_bounds__(256) void k_scan_rows(int64_t n, const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, int64_t nnz,
                                                    unsigned long long* __restrict__ band,
-                                                   unsigned int* __restrict__ flags,
-                                                   unsigned long long* __restrict__ blknorm) {
+                                                   unsigned int* __restrict__ flags) {
   __shared__ unsigned long long sb[256];
-  __shared__ double sn[256];
   __shared__ unsigned int sf[256];
-  __shared__ int sblk[256];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long bw = 0;
   unsigned int f = 0;
-  double rowsum = 0.0;
-  int blk = -1;
   if (r == 0 && (row_ptr[0] != 0 || row_ptr[n] != nnz)) f |= 1u;
   if (r < n) {
     const int64_t a = row_ptr[r], b = row_ptr[r + 1];
-    blk = find_block(part, p, r);
     if (b < a || a < 0 || b > nnz) {
       f |= 1u;
     } else {
-      const int64_t s = part[blk], e = part[blk + 1];
       for (int64_t q = a; q < b; ++q) {
         const int64_t c = col[q];
         const double v = val[q];
@@ -52,33 +43,42 @@ __global__ __launch_bounds__(256) void k_scan_rows(int64_t n, int p, const int64
         if (!isfinite(v)) f |= 4u;
         const unsigned long long d = (unsigned long long)(c > r ? c - r : r - c);
         bw = d > bw ? d : bw;
-        if (c >= s && c < e) rowsum += fabs(v);
       }
     }
   }
   const int t = threadIdx.x;
-  sb[t] = bw; sf[t] = f; sn[t] = rowsum; sblk[t] = blk;
+  sb[t] = bw; sf[t] = f;
   __syncthreads();
-  const int b0 = sblk[0];
-  int blast = -1;
-  for (int i = blockDim.x - 1; i >= 0; --i)
-    if (sblk[i] >= 0) { blast = sblk[i]; break; }
-  const bool one_block = b0 >= 0 && b0 == blast;
   for (int s2 = 128; s2 > 0; s2 >>= 1) {
     if (t < s2) {
       sb[t] = sb[t] > sb[t + s2] ? sb[t] : sb[t + s2];
       sf[t] |= sf[t + s2];
-      if (one_block) sn[t] = fmax(sn[t], sn[t + s2]);
     }
     __syncthreads();
   }
   if (t == 0) {
     if (sf[0]) atomicOr(flags, sf[0]);
     atomicMax(band, sb[0]);
-    // non-negative doubles order like their bit patterns
-    if (one_block) atomicMax(&blknorm[b0], (unsigned long long)__double_as_longlong(sn[0]));
   }
-  if (!one_block && blk >= 0) atomicMax(&blknorm[blk], (unsigned long long)__double_as_longlong(rowsum));
+}
+
+// Pivot threshold of every row: 1e3 eps max_j |a_rj| over the row's entries
+// inside its own block, written at the row's place in the padded layout.  A
+// pivot at or below it is numerically zero on the scale of its own row, so
+// badly scaled but nonsingular blocks (coefficients over many decades) pass.
+__global__ void k_row_thresh(int64_t n, int p, const int64_t* __restrict__ part,
+                             const BlockInfo* __restrict__ blocks, const int64_t* __restrict__ row_ptr,
+                             const int32_t* __restrict__ col, const double* __restrict__ val, double scale,
+                             double* __restrict__ thresh) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const BlockInfo B = blocks[find_block(part, p, r)];
+  double mx = 0.0;
+  for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+    const int64_t c = col[q];
+    if (c >= B.s && c < B.s + B.n) mx = fmax(mx, fabs(val[q]));
+  }
+  thresh[B.voff + B.pad + (r - B.s)] = scale * mx;
 }
 
 template <typename T>
@@ -174,19 +174,13 @@ __global__ void k_mask(int p, int t, double delta, const BlockInfo* __restrict__
   }
 }
 
-__global__ void k_thresh(int p, double eps, const unsigned long long* __restrict__ blknorm,
-                         double* __restrict__ thresh) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < p) thresh[i] = 1e3 * eps * __longlong_as_double((long long)blknorm[i]);
-}
-
 // ------------------------------------------------------------------ launchers
 void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
-                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags,
-                unsigned long long* blknorm, hipStream_t s) {
+                const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags, hipStream_t s) {
+  (void)p;
+  (void)part;
   const int64_t nb = (n + 255) / 256;
-  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)nb), dim3(256), 0, s, n, p, part, row_ptr, col,
-                     val, nnz, band, flags, blknorm);
+  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)nb), dim3(256), 0, s, n, row_ptr, col, val, nnz, band, flags);
 }
 
 void fill_f64(double* ptr, int64_t count, double v, hipStream_t s) {
@@ -230,8 +224,12 @@ void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
                        (float*)spikes);
 }
 
-void setup_thresh(int p, double eps, const unsigned long long* blknorm, double* thresh, hipStream_t s) {
-  hipLaunchKernelGGL(k_thresh, dim3((p + 255) / 256), dim3(256), 0, s, p, eps, blknorm, thresh);
+void setup_row_thresh(int64_t n, int p, int64_t Np, const int64_t* part, const BlockInfo* blocks,
+                      const int64_t* row_ptr, const int32_t* col, const double* val, double eps, double* thresh,
+                      hipStream_t s) {
+  fill_f64(thresh, Np, 0.0, s);
+  hipLaunchKernelGGL(k_row_thresh, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, p, part, blocks, row_ptr,
+                     col, val, 1e3 * eps, thresh);
 }
 
 }  // namespace ddps

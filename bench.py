@@ -56,7 +56,7 @@ def build_workload(name):
     return configs.BUILDERS[name]()
 
 
-def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None):
+def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None, exec_form=None):
     import torch
     from paper_1008_1700_amd import ddps
     A = d["A"]
@@ -70,7 +70,11 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         f = torch.from_numpy(np.ascontiguousarray(fh.T)).cuda()        # row j = right-hand side j
         x = torch.zeros(k, A.n, dtype=torch.float64, device="cuda")
     val = S.val
-    tune = ddps.ddps_autotune(S.h)        # execution form (stream groups, tile policy), untimed
+    if exec_form is None:
+        tune = ddps.ddps_autotune(S.h)        # execution form (stream groups, tile policy), untimed
+    else:
+        ddps.ddps_set_execution(S.h, exec_form[0], False, exec_form[1])
+        tune = dict(streams=exec_form[0], tile_policy=exec_form[1], factor_ms=None)
 
     def step():
         ddps.ddps_refactor_values(S.h, val)
@@ -95,6 +99,21 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
     tim = ddps.ddps_timing_read(S.h, timing_kind)
     rc, info = infos[-1]
     xs = x.cpu().numpy()
+    # one more (untimed) step with the solve-phase GEMV launches timed
+    gemv = dict(launches=0, ms=0.0, bytes=0.0, per_kind={})
+    for kind in ("sweep", "reduced", "retrieval"):
+        ddps.ddps_timing_read(S.h, kind)
+        ddps.ddps_timing_enable(S.h, kind, True)
+    step()
+    torch.cuda.synchronize()
+    for kind in ("sweep", "reduced", "retrieval"):
+        ddps.ddps_timing_enable(S.h, kind, False)
+        tk = ddps.ddps_timing_read(S.h, kind)
+        gemv["launches"] += tk["launches"]
+        gemv["ms"] += tk["ms"]
+        gemv["bytes"] += tk["bytes"]
+        gemv["per_kind"][kind] = dict(launches=tk["launches"], ms=tk["ms"],
+                                      GBps=tk["bytes"] / (tk["ms"] * 1e-3) / 1e9 if tk["ms"] > 0 else None)
     graph_ms = None
     if graph_steps:
         ddps.ddps_set_execution(S.h, tune["streams"], True, tune["tile_policy"])
@@ -121,13 +140,41 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
                     ms_per_step=tim["ms"] / steps, flops_per_step=tim["flops"] / steps,
                     bytes_per_step=tim["bytes"] / steps),
         mem_gb=ddps.ddps_memory(S.h) / 1e9,
-        inner_tol=inner_tol,
+        inner_tol=inner_tol, gemv=gemv,
         exec=dict(tune, graph_ms_per_step=graph_ms),
     )
     S.close()
     del f, x
     torch.cuda.empty_cache()
     return out
+
+
+def recorded_traffic(config, mode, launches_per_step):
+    """HBM bytes per grouped-GEMM launch from the counter runs recorded in
+    profiles/*_traffic.md (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled
+    by what the counter reads for a plain copy of known size).  None when no
+    record matches this workload and mode, or when the GEMM source changed
+    since the counters were taken (its hash differs)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1008_1700_amd", "csrc", "k_gemm.hip")
+    try:
+        md5 = hashlib.md5(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None, None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        for line in open(path):
+            if not line.startswith("traffic: "):
+                continue
+            rec = json.loads(line[len("traffic: "):])
+            if rec.get("config") != config or rec.get("mode") != mode:
+                continue
+            if rec.get("k_gemm_md5") != md5:
+                return None, os.path.basename(path) + " (stale: GEMM source changed)"
+            per_launch = rec["fetch_kib_per_launch"] * 1024 * rec["fetch_scale"] + \
+                rec["write_kib_per_launch"] * 1024 * rec["write_scale"]
+            return per_launch, os.path.basename(path)
+    return None, None
 
 
 def band_lu_spike_flops(d):
@@ -238,6 +285,19 @@ def run_c4(args):
     print(json.dumps(res), flush=True)
 
 
+def copy_probe(gib=1.0):
+    """A plain device-to-device copy of a known size, for scaling the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) of a profiled run."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +312,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-6, help="reduced-solve tolerance, timed mode")
     ap.add_argument("--inner-tol-f64", type=float, default=1e-9, help="reduced-solve tolerance, FP64 mode")
     ap.add_argument("--graph-steps", type=int, default=2, help="extra steps timed with the factor graph")
+    ap.add_argument("--exec", default=None, help="fixed execution form 'streams,tile_policy' instead of the autotuner")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the calibration copy (3 x 1 GiB)")
     ap.add_argument("--c4-steps", type=int, default=300)
     ap.add_argument("--c4-train", type=int, default=200)
     ap.add_argument("--c4-epochs", type=int, default=200)
@@ -262,40 +324,60 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.config == "c4":
         run_c4(args)
         return
+    exec_form = tuple(int(v) for v in args.exec.split(",")) if args.exec else None
     log(f"building workload {args.config}")
     d = build_workload(args.config)
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
-    res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps)
+    res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps,
+                   exec_form=exec_form)
     log(f"{args.mode}: {json.dumps(res)}")
     base = None
     if not args.no_baseline and args.mode != "f64":
         from paper_1008_1700_amd import ddps
         try:
             base = run_mode(d, "f64", args.steps, args.warmup, args.tol, args.inner_tol_f64,
-                            graph_steps=args.graph_steps)
+                            graph_steps=args.graph_steps, exec_form=exec_form)
         except ddps.DDPSError as e:
             # FP64 factors and spikes beyond the device memory: the paper's failure F1
             base = dict(mode="f64", status=str(e), ms_per_step=None)
         log(f"f64: {json.dumps(base)}")
     k = res["kernel"]
     kms = k["ms_per_step"]
-    achieved = k["flops_per_step"] / (kms * 1e-3) if kms > 0 else 0.0
     peak = PEAKS[args.mode]
-    # achieved: flops the grouped GEMM launches execute (triangular K ranges
-    # clipped at tile granularity) over their summed launch durations; with
-    # stream groups launches overlap, so this understates the rate.  The
-    # phase rate divides the band-LU + spike algorithmic flops by the factor
-    # phase's wall time.
+    # achieved: the band-LU + spike algorithmic flops of stages 2 and 4 per
+    # step over the summed durations of the grouped GEMM launches (HIP events
+    # on each launch's stream, timed steps).  With stream groups launches of
+    # different groups overlap, so the summed durations overstate the GEMM's
+    # own time and the rate is a lower bound.  mfma_rate counts the products
+    # the launches execute (tile-granular triangles; three bf16 products per
+    # split product).
     alg = band_lu_spike_flops(d)
+    achieved = alg / (kms * 1e-3) if kms > 0 else 0.0
+    split = 3.0 if args.mode == "bf16x3" else 1.0
+    traffic, traffic_src = recorded_traffic(args.config, args.mode, k["launches_per_step"])
     roof = dict(bound="mfma", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                frac=achieved / peak, traffic=None, kernel="k_gemm_bf16 / k_gemm_std (grouped GEMM, factor + spikes)",
+                frac=achieved / peak, traffic=traffic,
+                kernel="k_gemm_bf16 / k_gemm_std (grouped GEMM of stages 2 and 4)",
                 launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms,
-                flops_per_step=k["flops_per_step"],
+                avg_launch_us=kms * 1e3 / max(k["launches_per_step"], 1),
+                algorithmic_flops_per_step=alg,
+                mfma_rate=k["flops_per_step"] * split / (kms * 1e-3) / 1e12 if kms > 0 else None,
+                traffic_unit="HBM bytes per launch", traffic_source=traffic_src,
                 factor_phase_rate=alg / (res["factor_ms"] * 1e-3) / 1e12)
+    g = res.get("gemv")
+    roof_gemv = None
+    if g and g["ms"] > 0:
+        bw = g["bytes"] / (g["ms"] * 1e-3)
+        roof_gemv = dict(bound="hbm", achieved=bw / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s", frac=bw / HBM_PEAK,
+                         kernel="k_gemv (reduced products, block sweeps, retrieval)", launches=g["launches"],
+                         algorithmic_bytes=g["bytes"], ms=g["ms"], per_kind=g["per_kind"])
     cpu = None if args.no_cpu else cpu_baseline(d)
     out = {
         "metric": "DDPS time-to-solution @rel.resid 1e-10, mixed vs plain FP64" + (
@@ -317,6 +399,7 @@ def main():
         "speedup_vs_f64": (base["ms_per_step"] / res["ms_per_step"]) if base and base.get("ms_per_step") else None,
         "algorithmic_flops_factor": band_lu_spike_flops(d),
         "roofline": roof,
+        "roofline_gemv": roof_gemv,
         "cpu_baseline": cpu,
     }
     if cpu:

@@ -118,7 +118,8 @@ struct ddps_ctx {
   std::vector<int> group_of;
   std::vector<Launch> sch_fwd, sch_bwd, sch_retr;
   int groups = 1;          // stream groups of the factor schedule
-  int tile_policy = 0;     // 0: 128 x 128 GEMM tiles where every problem allows, 1: 64 x 64 only
+  int tile_policy = 0;     // 0: 128 x 128 GEMM tiles where every problem allows, 1: 64 x 64 only,
+                           // 2: 256 x 128 (bf16 arithmetic) where every problem allows
   bool use_graph = false;  // capture ddps_factor once as a HIP graph, then replay it
   hipStream_t fstream = nullptr;          // internal stream of the factorisation
   std::vector<hipStream_t> gstream;       // one per group beyond the first
@@ -276,11 +277,13 @@ struct ScheduleBuilder {
   // GEMM launches: 128 x 128 tiles when every problem is at least that
   // large, else 64 x 64; assigns each problem its first workgroup.
   int finish_gemm() {
-    // 128 x 128 tiles at two workgroups per CU measured fastest for every
-    // dtype on 1024-sized problems (the 256 x 128 bf16 tile runs at one)
-    int mode = h->tile_policy == 1 ? 0 : 1;
-    for (size_t q = (size_t)off; q < gemm.size(); ++q)
+    // the largest tile every problem of the launch fills: 256 x 128 (bf16
+    // arithmetic, policy 2), 128 x 128, else 64 x 64
+    int mode = h->tile_policy == 1 ? 0 : (h->tile_policy == 2 && h->gdt >= 2) ? 2 : 1;
+    for (size_t q = (size_t)off; q < gemm.size(); ++q) {
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
+      else if (mode == 2 && gemm[q].M < 256) mode = 1;
+    }
     int BM, BN;
     gemm_tile_shape(h->gdt, mode, &BM, &BN);
     nwg = 0;
@@ -1710,7 +1713,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
 }
 
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
-  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 1) return DDPS_E_ARG;
+  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 2) return DDPS_E_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipStreamSynchronize(h->fstream));
   h->groups = streams > 0 ? streams : default_groups(h);
@@ -1801,7 +1804,7 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
   int rc;
   if (!cache_lookup(cache_path, key, &bs, &bq, &bms)) {
     bms = 1e300;
-    for (int q = 0; q <= 1; ++q)
+    for (int q = 0; q <= (h->gdt >= 2 ? 2 : 1); ++q)
       for (int g : {1, 2, 4, 8}) {
         if (g > h->p) continue;
         if ((rc = ddps_set_execution(h, g, 0, q))) return rc;

@@ -208,13 +208,13 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
 // ------------------------------------------------------------------------
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <bool SPLIT, int BM, int BN, int OCC = 1>
+template <bool SPLIT, int BM, int BN, int OCC = 1, int ST = 1, int BK = 32>
 __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
-  constexpr int BK = 32, LDK = BK + 8;
+  constexpr int LDK = BK + 8;
   constexpr int MB = BM / 64, NB = BN / 64;     // 32 x 32 blocks per wave (wave tile BM/2 x BN/2)
   constexpr int NS = SPLIT ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NS][BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BN][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 As[ST][NS][BM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][NS][BN][LDK];
 
   const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
@@ -236,11 +236,14 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  // A chunk BM x 32: thread -> 4 consecutive rows (a float4 per k) x AK k.
-  // B chunk 32 x BN: thread -> one column, BKT consecutive k (float4 loads).
+  // A chunk BM x BK: thread -> 4 consecutive rows (a float4 per k) x AK k
+  // (float4 loads along the contiguous row index).
+  // B chunk BK x BN: thread -> one column, BKT consecutive k (float4 loads,
+  // 16-byte LDS stores).
   constexpr int AROWG = BM / 4;
   constexpr int AK = BK * AROWG / 256;
   constexpr int BKT = BK * BN / 256;
+  static_assert(AK >= 1 && BKT % 8 == 0, "chunk split");
   const int arg = tid % AROWG, akg = tid / AROWG;
   const int ar = I0 + 4 * arg;
   const int bn = tid % BN, bkg = tid / BN;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
   const int bcol_ld = min(bc, P.N - 1);
   float4 ra[AK];
   float4 rb[BKT / 4];
-  auto load = [&](int k0) {
+  auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < AK; ++i)
       ra[i] = *(const float4*)(A + (int64_t)(k0 + akg * AK + i) * P.lda + arow_ld);
@@ -258,10 +261,10 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
     for (int i = 0; i < BKT / 4; ++i) rb[i] = *(const float4*)(bp + 4 * i);
   };
   typedef __bf16 bfa __attribute__((ext_vector_type(AK)));
-  auto store_chunk = [&](int k0) {
-    // masks only where the chunk crosses a packed triangle's diagonal or the edge
-    const bool am = a_edge || ((a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM);
-    const bool bm = b_edge || ((b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN);
+  // Stage one chunk into LDS as bf16 (hi, and lo = x - hi when split).  The
+  // masked form applies the packed-triangle and edge masks; it is taken only
+  // for chunks that cross a packed triangle's diagonal or the problem edge.
+  auto store_chunk = [&](int st, int k0, bool am, bool bm) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = ar + q;
@@ -273,57 +276,92 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
         h[i] = (__bf16)x;
         if (SPLIT) l[i] = (__bf16)(x - (float)h[i]);
       }
-      *(bfa*)&As[0][4 * arg + q][akg * AK] = h;
-      if (SPLIT) *(bfa*)&As[NS - 1][4 * arg + q][akg * AK] = l;
+      *(bfa*)&As[st][0][4 * arg + q][akg * AK] = h;
+      if (SPLIT) *(bfa*)&As[st][NS - 1][4 * arg + q][akg * AK] = l;
     }
 #pragma unroll
-    for (int i4 = 0; i4 < BKT / 4; ++i4) {
-      bf16x4 h, l;
+    for (int j = 0; j < BKT / 8; ++j) {
+      bf16x8 h, l;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float x = rb[i4][q];
-        if (bm) x = select_op(x, k0 + bkg * BKT + 4 * i4 + q, bc, b_lu, b_up, 1 << 30, P.N);
-        h[q] = (__bf16)x;
-        if (SPLIT) l[q] = (__bf16)(x - (float)h[q]);
+      for (int e = 0; e < 8; ++e) {
+        float x = rb[2 * j + e / 4][e % 4];
+        if (bm) x = select_op(x, k0 + bkg * BKT + 8 * j + e, bc, b_lu, b_up, 1 << 30, P.N);
+        h[e] = (__bf16)x;
+        if (SPLIT) l[e] = (__bf16)(x - (float)h[e]);
       }
-      *(bf16x4*)&Bs[0][bn][bkg * BKT + 4 * i4] = h;
-      if (SPLIT) *(bf16x4*)&Bs[NS - 1][bn][bkg * BKT + 4 * i4] = l;
+      *(bf16x8*)&Bs[st][0][bn][bkg * BKT + 8 * j] = h;
+      if (SPLIT) *(bf16x8*)&Bs[st][NS - 1][bn][bkg * BKT + 8 * j] = l;
+    }
+  };
+  auto stage = [&](int st, int k0) __attribute__((always_inline)) {
+    const bool am = a_edge || ((a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM);
+    const bool bm = b_edge || ((b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN);
+    if (am || bm) store_chunk(st, k0, am, bm);
+    else store_chunk(st, k0, false, false);
+  };
+  auto compute = [&](int st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int kk = ks * 16 + 8 * (lane >> 5);
+      bf16x8 xh[NB], xl[NB], yh[MB], yl[MB];
+#pragma unroll
+      for (int ni = 0; ni < NB; ++ni) {
+        const int n = wn * (BN / 2) + ni * 32 + (lane & 31);
+        xh[ni] = *(const bf16x8*)&Bs[st][0][n][kk];
+        if (SPLIT) xl[ni] = *(const bf16x8*)&Bs[st][NS - 1][n][kk];
+      }
+#pragma unroll
+      for (int mi = 0; mi < MB; ++mi) {
+        const int m = wm * (BM / 2) + mi * 32 + (lane & 31);
+        yh[mi] = *(const bf16x8*)&As[st][0][m][kk];
+        if (SPLIT) yl[mi] = *(const bf16x8*)&As[st][NS - 1][m][kk];
+      }
+      // one term over every block before the next, so consecutive MFMAs
+      // write different accumulators (small terms first)
+      if (SPLIT) {
+#pragma unroll
+        for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NB; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ni], yh[mi], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+        for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NB; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yl[mi], acc[mi][ni], 0, 0, 0);
+      }
+#pragma unroll
+      for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NB; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yh[mi], acc[mi][ni], 0, 0, 0);
     }
   };
 
   if (kb < ke) {
-    load(kb);
-    for (int kcur = kb; kcur < ke; kcur += BK) {
-      __syncthreads();             // previous chunk's LDS reads are done
-      store_chunk(kcur);
+    if (ST == 2) {
+      // two LDS stages: the next chunk is loaded before and staged after the
+      // current chunk's products, one barrier per chunk
+      load(kb);
+      stage(0, kb);
       __syncthreads();
-      if (kcur + BK < ke) load(kcur + BK);
-#pragma unroll
-      for (int ks = 0; ks < BK / 16; ++ks) {
-        const int kk = ks * 16 + 8 * (lane >> 5);
-        bf16x8 xh[NB], xl[NB], yh[MB], yl[MB];
-#pragma unroll
-        for (int ni = 0; ni < NB; ++ni) {
-          const int n = wn * (BN / 2) + ni * 32 + (lane & 31);
-          xh[ni] = *(const bf16x8*)&Bs[0][n][kk];
-          if (SPLIT) xl[ni] = *(const bf16x8*)&Bs[NS - 1][n][kk];
-        }
-#pragma unroll
-        for (int mi = 0; mi < MB; ++mi) {
-          const int m = wm * (BM / 2) + mi * 32 + (lane & 31);
-          yh[mi] = *(const bf16x8*)&As[0][m][kk];
-          if (SPLIT) yl[mi] = *(const bf16x8*)&As[NS - 1][m][kk];
-        }
-#pragma unroll
-        for (int mi = 0; mi < MB; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < NB; ++ni) {
-            if (SPLIT) {
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ni], yh[mi], acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yl[mi], acc[mi][ni], 0, 0, 0);
-            }
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yh[mi], acc[mi][ni], 0, 0, 0);
-          }
+      int st = 0;
+      for (int kcur = kb; kcur < ke; kcur += BK) {
+        const bool more = kcur + BK < ke;
+        if (more) load(kcur + BK);
+        compute(st);
+        if (more) stage(st ^ 1, kcur + BK);
+        __syncthreads();
+        st ^= 1;
+      }
+    } else {
+      load(kb);
+      for (int kcur = kb; kcur < ke; kcur += BK) {
+        __syncthreads();             // previous chunk's LDS reads are done
+        stage(0, kcur);
+        __syncthreads();
+        if (kcur + BK < ke) load(kcur + BK);
+        compute(0);
       }
     }
   }
@@ -367,8 +405,8 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
   const bool split = dtype == 2;
   switch (mode) {
     case 2:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);
       break;
     case 1:
       if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2>), g, b, 0, s, probs, nprob);

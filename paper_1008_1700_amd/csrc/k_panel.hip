@@ -41,6 +41,7 @@ __global__ __launch_bounds__(64) void k_panel(const PanelProb* __restrict__ prob
   T a[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) a[c] = D[(int64_t)c * P.ld + r];
+  const double th = thresh[P.vrow0 + r];   // pivot threshold of this lane's row
 
   // Every loop is fully unrolled: register indices are compile-time
   // constants and the triangular loop bounds prune at compile time.
@@ -49,17 +50,15 @@ __global__ __launch_bounds__(64) void k_panel(const PanelProb* __restrict__ prob
     if (r == k) {
 #pragma unroll
       for (int c = k; c < N; ++c) Ur[k][c] = a[c];
-    }
-    __syncthreads();   // a single wave: orders the LDS accesses only
-    const T piv = Ur[k][k];
-    if (r == 0) {
-      const double av = fabs((double)piv);
-      if (!(av > thresh[P.vrow0 + k]) || !(av <= 1.7e308)) {
+      const double av = fabs((double)a[k]);
+      if (!(av > th) || !(av <= 1.7e308)) {
         const unsigned long long key =
             ((unsigned long long)P.block << 40) | (unsigned long long)(P.row0 + k);
         atomicMin(bad, key);
       }
     }
+    __syncthreads();   // a single wave: orders the LDS accesses only
+    const T piv = Ur[k][k];
     if (r > k) {
       const T l = a[k] / piv;
       Lc[k][r] = l;

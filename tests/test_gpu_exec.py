@@ -104,3 +104,24 @@ def test_autotune_and_cache(tmp_path):
         assert r2["factor_ms"] == pytest.approx(r1["factor_ms"], rel=1e-3)
     finally:
         S.close()
+
+
+def test_bf16x3_tile_policies_agree():
+    """The 256 x 128 bf16 tile (policy 2), the 128 x 128 tile (policy 0) and
+    the 64 x 64 tile (policy 1) compute the same split-bf16 products; tiles
+    with t = 256 let policy 2 take the large tile on most launches."""
+    from paper_1008_1700_amd import ddps
+    d = configs.small_banded(4, [700, 900, 600, 820], 200, 23)
+    xs = {}
+    for policy in (0, 2, 1):
+        S = make_solver(d, dtype="bf16x3", inner_tol=1e-8)
+        try:
+            ddps.ddps_set_execution(S.h, 1, False, policy)
+            S.factor()
+            x, info = _solve(S, d, tol=1e-11)
+            assert info.relres_inf <= 1e-11
+            xs[policy] = x
+        finally:
+            S.close()
+    assert relerr(xs[2], d["x_star"]) <= 1e-9
+    assert relerr(xs[2], xs[0]) <= 1e-10 and relerr(xs[1], xs[0]) <= 1e-10

@@ -35,7 +35,7 @@ using namespace ddps;
 
 namespace {
 
-enum LaunchKind { LK_GEMM = 0, LK_PANEL = 1, LK_GEMV = 2 };
+enum LaunchKind { LK_GEMM = 0, LK_PANEL = 1, LK_GEMV = 2, LK_TIPMV = 3 };
 enum TimingKind { TK_GEMM = 0, TK_PANEL = 1, TK_SWEEP = 2, TK_RSPMV = 3, TK_RETR = 4, TK_CSR = 5, TK_N = 6 };
 
 struct Launch {
@@ -93,6 +93,8 @@ struct ddps_ctx {
   double* d_val = nullptr;
   BlockInfo* d_blk = nullptr;
   void *d_tiles = nullptr, *d_spikes = nullptr, *d_scratch = nullptr;
+  void* d_tips = nullptr;   // spike tips packed row-major (rows of G^), 2(p-1) parts of t x 2t
+  int tip_nseg = 0;         // > 0: reduced products on the packed tips (R <= 2 and 2t short enough)
   unsigned long long *d_colnorm = nullptr, *d_bad = nullptr, *d_band = nullptr;
   unsigned int* d_flags = nullptr;
   double* d_thresh = nullptr;   // per padded row: pivot threshold
@@ -619,7 +621,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
   sb.end(h->sch_retr);
   // reduced products
   auto reduced = [&](const double* X, double* Y, const double* dotv, int dflags) {
-    sb.begin(LK_GEMV);
+    sb.begin(h->tip_nseg > 0 ? LK_TIPMV : LK_GEMV);
     for (int i = 0; i < p && p > 1; ++i) {
       const BlockInfo& B = h->blk[i];
       for (int part = 0; part < 2; ++part) {
@@ -627,8 +629,15 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
         if (part == 1 && i == p - 1) continue;
         const int64_t ro = part == 0 ? (int64_t)(2 * i - 1) * t : (int64_t)2 * i * t;
         GemvProb G{};
-        G.A = h->spike(i, part == 0 ? B.pad : B.N - t, 0);
-        G.lda = B.N;
+        if (h->tip_nseg > 0) {
+          // packed part q = 2i - 1 (first t rows of block i) or 2i (last t rows)
+          const int64_t q = part == 0 ? 2 * i - 1 : 2 * i;
+          G.A = (const char*)h->d_tips + (size_t)q * t * 2 * t * h->elt;
+          G.lda = 2 * t;
+        } else {
+          G.A = h->spike(i, part == 0 ? B.pad : B.N - t, 0);
+          G.lda = B.N;
+        }
         G.x1 = X + (i > 0 ? (int64_t)2 * (i - 1) * t : 0);
         G.x2 = X + (i < p - 1 ? (int64_t)(2 * i + 1) * t : 0);
         G.split = t;
@@ -660,9 +669,12 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
   switch (L.kind) {
     case LK_GEMM: launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, s); break;
     case LK_PANEL: launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, s); break;
+    case LK_TIPMV:
+      launch_tipmv(h->sdt, R, h->tip_nseg, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
+      break;
     default: launch_gemv(h->sdt, R, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s); break;
   }
-  h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV ? R : 1), L.bytes, s);
+  h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV || L.kind == LK_TIPMV ? R : 1), L.bytes, s);
   return DDPS_OK;
 }
 int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, const double* dotv,
@@ -716,7 +728,12 @@ int enqueue_factor(ddps_ctx* h) {
   int rc = do_scatter(h, f);
   if (rc) return rc;
   const int G = (int)h->sch_group.size();
-  if (G <= 1) return G == 1 ? run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f) : DDPS_OK;
+  if (G <= 1) {
+    if (G == 1 && (rc = run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f))) return rc;
+    if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
+    HIPCHK(hipGetLastError());
+    return DDPS_OK;
+  }
   HIPCHK(hipEventRecord(h->fork_ev, f));
   for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->gstream[g - 1], h->fork_ev, 0));
   if ((rc = run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f))) return rc;
@@ -725,6 +742,8 @@ int enqueue_factor(ddps_ctx* h) {
     HIPCHK(hipEventRecord(h->gevent[g - 1], h->gstream[g - 1]));
   }
   for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(f, h->gevent[g - 1], 0));
+  if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
+  HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
 
@@ -1125,6 +1144,9 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   size_t need = 0;
   need += (size_t)h->ntiles * t * t * h->elt;
   need += (size_t)h->nspike * h->elt;
+  // packed tips (2(p-1) parts of t x 2t = m x 2t) for one or two right-hand sides
+  h->tip_nseg = (R <= 2 && p > 1) ? tipmv_segments(h->sdt, t) : 0;
+  if (h->tip_nseg > 0) need += (size_t)m * 2 * t * h->elt;
   need += (size_t)p * h->scr_per_block * h->elt;
   need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
   need += (size_t)h->Np * R * 8 * 2 + (size_t)h->Np * 8;
@@ -1143,6 +1165,10 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->d_tiles = vp;
   if ((rc = h->alloc_raw(vp, (size_t)std::max<int64_t>(h->nspike, 1) * h->elt))) return fail(rc);
   h->d_spikes = vp;
+  if (h->tip_nseg > 0) {
+    if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
+    h->d_tips = vp;
+  }
   if ((rc = h->alloc_raw(vp, (size_t)p * h->scr_per_block * h->elt))) return fail(rc);
   h->d_scratch = vp;
   if ((rc = h->alloc(h->d_colnorm, (int64_t)p * 2 * t)) || (rc = h->alloc(h->d_mask, std::max<int64_t>(m, 1))) ||

@@ -139,6 +139,14 @@ void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* th
                   unsigned long long* bad, hipStream_t s);
 void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
+// reduced-matrix product on the packed tips (same records as launch_gemv,
+// A = first packed row, lda = 2t; nrhs 1 or 2; nseg from tipmv_segments, 0 if
+// 2t is too long for the register-held right-hand side) and the packing of
+// the tips after a factorisation
+int tipmv_segments(int dtype, int t);
+void launch_tipmv(int dtype, int nrhs, int nseg, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
+void pack_tips(int dtype, int p, int t, const BlockInfo* blocks, const void* spikes, void* tips, hipStream_t s);
 
 void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
                 const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags, hipStream_t s);

@@ -112,6 +112,176 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvProb* __restrict__ probs
   }
 }
 
+// ------------------------------------------------------------------------
+// Reduced-matrix product on packed spike tips.  The rows of G^ are the
+// first and last t rows of each spike G_i (2t columns each), which inside
+// the column-major spikes are 4t-byte column pieces N_i apart.  After every
+// factorisation they are packed row-major (k_pack_tips), and the product
+// streams each row as one contiguous run: a wave owns a row at a time, its
+// lanes read consecutive 16-byte pieces of it, the right-hand-side entries
+// come from L1/L2 (2t values shared by every row of the part), and the row
+// sum is a wave reduction.  Same problem records, flags and partial-sum
+// layout as k_gemv (A = first packed row, lda = row length 2t).
+// ------------------------------------------------------------------------
+template <typename T, int R, int NSEG>
+__global__ __launch_bounds__(256) void k_tipmv(const GemvProb* __restrict__ probs, int nprob,
+                                               int64_t ldx, int64_t ldy,
+                                               const double* __restrict__ dotv,
+                                               double* __restrict__ partial,
+                                               const int32_t* __restrict__ stop) {
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int RPW = 16;                       // rows per wave (64 per workgroup)
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  __shared__ double red[4][R][2];
+  if (stop) {
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < R; ++j) all &= stop[j] != KS_RUNNING;
+    if (all) return;
+  }
+  const int wg = blockIdx.x;
+  const GemvProb& P = probs[find_gemv(probs, nprob, wg)];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fl = P.flags;
+  const int cb = P.cb, ce = P.ce, split = P.split;
+  const int rbase = (wg - P.wg0) * 64 + wave * RPW;
+  // the right-hand-side entries of this lane's columns, once for all rows
+  double xr[NSEG][VEC][R];
+#pragma unroll
+  for (int sg = 0; sg < NSEG; ++sg)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int c = cb + (sg * 64 + lane) * VEC + e;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        double v = 0.0;
+        if (c < ce) v = c < split ? P.x1[c + j * ldx] : P.x2[(c - split) + j * ldx];
+        xr[sg][e][j] = v;
+      }
+    }
+  double dot[R], dd[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) dot[j] = dd[j] = 0.0;
+  for (int rr = 0; rr < RPW; ++rr) {
+    const int r = rbase + rr;
+    const T* __restrict__ Arow = (const T*)P.A + (int64_t)r * P.lda + cb;
+    vec_t a[NSEG];
+#pragma unroll
+    for (int sg = 0; sg < NSEG; ++sg) {
+      const int c0 = (sg * 64 + lane) * VEC;
+      if (cb + c0 < ce) a[sg] = *(const vec_t*)(Arow + c0);
+      else a[sg] = vec_t{};
+    }
+    double acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int sg = 0; sg < NSEG; ++sg)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[j] += (double)a[sg][e] * xr[sg][e][j];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        double v = acc[j];
+        if (fl & V_MASK) v *= P.mask[r];
+        if (fl & V_NEG) v = -v;
+        if (fl & V_YIN) v += P.yin[r + j * ldy];
+        P.yout[r + j * ldy] = v;
+        if (fl & V_DOT) dot[j] += dotv[P.dot_off + r + j * ldy] * v;
+        if (fl & V_DOT2) dd[j] += v * v;
+      }
+    }
+  }
+  if (fl & (V_DOT | V_DOT2)) {
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        red[wave][j][0] = dot[j];
+        red[wave][j][1] = dd[j];
+      }
+    __syncthreads();
+    if (tid < R) {
+      const int j = tid;
+      partial[((int64_t)wg * R + j) * 2 + 0] = (red[0][j][0] + red[1][j][0]) + (red[2][j][0] + red[3][j][0]);
+      partial[((int64_t)wg * R + j) * 2 + 1] = (red[0][j][1] + red[1][j][1]) + (red[2][j][1] + red[3][j][1]);
+    }
+  }
+}
+
+// Packs the spike tips row-major: part q (q = 0 .. 2(p-1)-1; block
+// i = (q+1)/2, its first t rows for q odd, its last t rows for q even) to
+// tips[q][r][c], r < t, c < 2t, through a 64 x 64 LDS tile so both the
+// column-major reads and the row-major writes are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_tips(const BlockInfo* __restrict__ blocks, int t,
+                                                   const T* __restrict__ spikes, T* __restrict__ tips) {
+  __shared__ T tile[64][65];
+  const int q = blockIdx.z;
+  const int i = (q + 1) / 2;
+  const BlockInfo B = blocks[i];
+  const int64_t row0 = (q & 1) ? B.pad : B.N - t;
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const T* __restrict__ G = spikes + B.goff;
+  T* __restrict__ out = tips + (int64_t)q * t * 2 * t;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int c = ty + 4 * k;
+    tile[c][tx] = G[(int64_t)(c0 + c) * B.N + row0 + r0 + tx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = ty + 4 * k;
+    out[(int64_t)(r0 + r) * 2 * t + c0 + tx] = tile[tx][r];
+  }
+}
+
+// segments of 64 x (16-byte piece) per row: 2t elements need ceil(2t / (64 VEC))
+int tipmv_segments(int dtype, int t) {
+  const int vec = dtype == 0 ? 2 : 4;
+  const int need = (2 * t + 64 * vec - 1) / (64 * vec);
+  for (int n : {4, 8, 16})
+    if (need <= n) return n;
+  return 0;   // longer rows: the product on the spikes themselves
+}
+
+template <typename T, int NSEG>
+static void tipmv_dispatch(int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+                           int64_t ldy, const double* dotv, double* partial, const int32_t* stop,
+                           hipStream_t s) {
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_tipmv<T, 1, NSEG>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop);
+  else
+    hipLaunchKernelGGL((k_tipmv<T, 2, NSEG>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop);
+}
+
+void launch_tipmv(int dtype, int nrhs, int nseg, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s) {
+  if (nwg <= 0 || nprob <= 0) return;
+#define DDPS_TIPMV(T)                                                                                   \
+  switch (nseg) {                                                                                       \
+    case 4: tipmv_dispatch<T, 4>(nrhs, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s); break;     \
+    case 8: tipmv_dispatch<T, 8>(nrhs, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s); break;     \
+    default: tipmv_dispatch<T, 16>(nrhs, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s); break;   \
+  }
+  if (dtype == 0) { DDPS_TIPMV(double) }
+  else { DDPS_TIPMV(float) }
+#undef DDPS_TIPMV
+}
+
+void pack_tips(int dtype, int p, int t, const BlockInfo* blocks, const void* spikes, void* tips, hipStream_t s) {
+  if (p < 2) return;
+  const dim3 g(2 * t / 64, t / 64, 2 * (p - 1)), b(256);
+  if (dtype == 0) hipLaunchKernelGGL(k_pack_tips<double>, g, b, 0, s, blocks, t, (const double*)spikes, (double*)tips);
+  else hipLaunchKernelGGL(k_pack_tips<float>, g, b, 0, s, blocks, t, (const float*)spikes, (float*)tips);
+}
+
 template <typename T>
 static void gemv_dispatch(int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                           int64_t ldy, const double* dotv, double* partial, const int32_t* stop,

@@ -56,13 +56,15 @@ def build_workload(name):
     return configs.BUILDERS[name]()
 
 
-def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None, exec_form=None):
+def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None, exec_form=None,
+             inner_prec=0):
     import torch
     from paper_1008_1700_amd import ddps
     A = d["A"]
     fh = d["f"]
     k = 1 if fh.ndim == 1 else fh.shape[1]
-    S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="refine", max_rhs=k)
+    S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="refine", max_rhs=k,
+                    inner_prec=inner_prec)
     if k == 1:
         f = torch.from_numpy(np.ascontiguousarray(fh)).cuda()
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
@@ -250,7 +252,8 @@ def run_c4(args):
     part = pde.slab_partition(ny, ny // p, nx)
     kinds = configs.c4_kinds(A1, nx)
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
-    S = ddps.Solver(A1, part, dtype=args.mode, inner_tol=itol, outer="refine", guess=True)
+    S = ddps.Solver(A1, part, dtype=args.mode, inner_tol=itol, outer="refine", guess=True,
+                    inner_prec=args.inner_prec if args.mode != "f64" else 0)
     tune = ddps.ddps_autotune(S.h)
     log(f"c4: n={A1.n} p={p} mode={args.mode} exec={tune}")
     t0 = time.perf_counter()
@@ -270,7 +273,8 @@ def run_c4(args):
         "data": "synthetic",
         "config": {"workload": "2D implicit-Euler upwind conv-diff 1024x1024, dt 1e-3, |v|=50 rotating 1.2 deg/step, "
                                "p=64, source 1, u0=0, tol 1e-10", "steps": args.c4_steps, "train_steps": args.c4_train,
-                   "net": "4 layers 4098-512-512-512-2048 bf16/FP32-accumulate, Adam", "epochs": args.c4_epochs},
+                   "net": "4 layers 4098-512-512-512-2048 bf16/FP32-accumulate, Adam", "epochs": args.c4_epochs,
+                   "inner_prec": args.inner_prec if args.mode != "f64" else 0},
         "eval_steps": len(ev),
         "solve_ms_prev": mean("prev_ms", ev), "solve_ms_learned": mean("learn_ms", ev),
         "inner_iters_prev": mean("prev_inner", ev), "inner_iters_learned": mean("learn_inner", ev),
@@ -311,6 +315,8 @@ def main():
     # defaults: the fastest tolerance of a sweep for each mode on this workload
     ap.add_argument("--inner-tol", type=float, default=1e-6, help="reduced-solve tolerance, timed mode")
     ap.add_argument("--inner-tol-f64", type=float, default=1e-9, help="reduced-solve tolerance, FP64 mode")
+    ap.add_argument("--inner-prec", type=int, default=0,
+                    help="inner BiCGStab preconditioner of the timed mode (0 none, 1 interface-local)")
     ap.add_argument("--graph-steps", type=int, default=2, help="extra steps timed with the factor graph")
     ap.add_argument("--exec", default=None, help="fixed execution form 'streams,tile_policy' instead of the autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="only run the calibration copy (3 x 1 GiB)")
@@ -335,8 +341,9 @@ def main():
     d = build_workload(args.config)
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
+    iprec = args.inner_prec if args.mode != "f64" else 0
     res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps,
-                   exec_form=exec_form)
+                   exec_form=exec_form, inner_prec=iprec)
     log(f"{args.mode}: {json.dumps(res)}")
     base = None
     if not args.no_baseline and args.mode != "f64":
@@ -393,7 +400,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS.get(args.config, args.config), "mode": args.mode},
+        "config": {"workload": WORKLOADS.get(args.config, args.config), "mode": args.mode, "inner_prec": iprec},
         "solve": {k2: v for k2, v in res.items() if k2 != "kernel"},
         "plain_f64": base and {k2: v for k2, v in base.items() if k2 != "kernel"},
         "speedup_vs_f64": (base["ms_per_step"] / res["ms_per_step"]) if base and base.get("ms_per_step") else None,

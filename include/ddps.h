@@ -79,6 +79,11 @@ typedef struct {
   int32_t factor_streams;  /* stream groups of the factorisation (blocks assigned longest
                               first); 0 = automatic */
   int32_t factor_graph;    /* 1: ddps_factor is captured once as a HIP graph and replayed */
+  int32_t inner_prec;      /* preconditioner of the inner BiCGStab: 0 = none (the paper's
+                              method, Section 4); 1 = z -> z - N z, N the interface-local part
+                              of G(c,c) (entries whose row and column lie at the same block
+                              boundary), right-preconditioned; it changes the iterates, not
+                              the solved system */
 } ddps_options;
 
 typedef struct {
@@ -97,7 +102,7 @@ typedef struct {
 /* Fills *opt with the defaults: delta 0, FP64 factors, inner_tol 1e-12,
  * inner_maxit 1000, outer_maxit 1000, iterative refinement, zero guess,
  * max_rhs 1, no memory budget, null stream, automatic stream groups, no
- * graph. */
+ * graph, no inner preconditioner. */
 void ddps_default_options(ddps_options* opt);
 
 /* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row

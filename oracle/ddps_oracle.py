@@ -307,6 +307,29 @@ class Preconditioner:
         """G^ z^ = z^ + G(c, c) z^ (stage 6.2 operator)."""
         return zc + self.g_times(zc)[self.c]
 
+    def local_matvec(self, zc):
+        """The interface-local part N of G(c, c) applied to z^ (values on c).
+
+        N keeps the entries of G(c, c) whose row and column lie at the same
+        block boundary: rows in the upper half of block i with columns of
+        block i-1, rows in the lower half of block i with columns of block
+        i+1 (every block has at least twice as many rows as its coupling
+        width, so the halves separate the two boundaries).  Used by the
+        optional inner preconditioner z -> z - N z."""
+        out = np.zeros(self.n)
+        for b, ci, Gi in zip(self.blocks, self.c_i, self.G):
+            if not ci.size:
+                continue
+            sel = np.array([self.pos.get(int(k), -1) for k in ci])
+            zz = np.where(sel >= 0, zc[np.maximum(sel, 0)], 0.0)
+            mid = (b.lo + b.hi) // 2
+            left = ci < b.lo
+            top = Gi[: mid - b.lo] @ np.where(left, zz, 0.0)
+            bot = Gi[mid - b.lo:] @ np.where(~left, zz, 0.0)
+            out[b.lo:mid] += top
+            out[mid:b.hi] += bot
+        return out[self.c]
+
     def ghat_dense(self):
         if self._Ghat is None:
             Gh = np.eye(self.m)
@@ -317,9 +340,11 @@ class Preconditioner:
         return self._Ghat
 
     # -- Figure 2 ------------------------------------------------------------
-    def apply(self, y, reduced="dense", inner_tol=1e-12, inner_maxit=1000, zhat0=None):
+    def apply(self, y, reduced="dense", inner_tol=1e-12, inner_maxit=1000, zhat0=None, inner_prec=None):
         """Solve P z = y.  Returns z, and a dict with g, g^, z^ and the inner
-        iteration record."""
+        iteration record.  inner_prec="local" preconditions the inner
+        BiCGStab with z -> z - N z (N = local_matvec), the first term of the
+        Neumann series of the interface-local blocks of G^."""
         y = np.asarray(y, dtype=np.float64)
         g = np.empty(self.n)
         for b, fac in zip(self.blocks, self.factors):                         # 6.1
@@ -331,8 +356,9 @@ class Preconditioner:
         elif reduced == "dense":                                              # 6.3
             zh = np.linalg.solve(self.ghat_dense(), gh)
         else:
+            M = (lambda v: v - self.local_matvec(v)) if inner_prec == "local" else None
             zh, inner = bicgstab(self.ghat_matvec, gh, x0=zhat0, tol=inner_tol,
-                                 maxit=inner_maxit)
+                                 maxit=inner_maxit, precond=M)
         z = g - self.g_times(zh)                                              # 6.4, 6.5
         return z, dict(g=g, ghat=gh, zhat=zh, inner=inner)
 

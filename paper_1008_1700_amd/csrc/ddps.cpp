@@ -106,6 +106,7 @@ struct ddps_ctx {
   double *d_ypad = nullptr, *d_vpad = nullptr;
   double *d_gh = nullptr, *d_zh = nullptr, *d_r = nullptr, *d_rt = nullptr, *d_p = nullptr,
          *d_v = nullptr, *d_s = nullptr, *d_tv = nullptr, *d_guess = nullptr;
+  double *d_mp = nullptr, *d_ms = nullptr;  // M^{-1}p, M^{-1}s of the locally preconditioned inner solve
   double *d_part_buf = nullptr, *d_sums = nullptr, *d_out = nullptr;
   KState* d_state = nullptr;
   int32_t* d_flag = nullptr;
@@ -131,6 +132,8 @@ struct ddps_ctx {
   hipGraphExec_t graph_exec = nullptr;
   bool capturing = false;
   Launch l_pv{}, l_st{}, l_zv{};  // reduced products: p->v (dot r~), s->t (dots), z->v
+  Launch l_lp{}, l_ls{};          // local preconditioner: p -> p - N p, s -> s - N s
+  Launch l_pvh{}, l_sth{};        // reduced products of the preconditioned directions
   int W1 = 0;
   bool factored = false;
   int guess_k = 0;
@@ -620,7 +623,10 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
   }
   sb.end(h->sch_retr);
   // reduced products
-  auto reduced = [&](const double* X, double* Y, const double* dotv, int dflags) {
+  // local = true: only the interface-local part N of G(c,c) (top rows of a
+  // block against its left-coupling columns, bottom rows against its right
+  // ones), Y = X - N X
+  auto reduced = [&](const double* X, double* Y, const double* dotv, int dflags, bool local = false) {
     sb.begin(h->tip_nseg > 0 ? LK_TIPMV : LK_GEMV);
     for (int i = 0; i < p && p > 1; ++i) {
       const BlockInfo& B = h->blk[i];
@@ -644,11 +650,15 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
         G.rows = t;
         G.cb = i == 0 ? t : 0;
         G.ce = i == p - 1 ? t : 2 * t;
+        if (local) {
+          G.cb = part == 0 ? 0 : t;
+          G.ce = part == 0 ? t : 2 * t;
+        }
         G.yin = X + ro;
         G.yout = Y + ro;
         G.mask = h->d_mask + ro;
         G.dot_off = ro;
-        G.flags = V_YIN | V_MASK | dflags;
+        G.flags = V_YIN | V_MASK | dflags | (local ? V_NEG : 0);
         G.tri = 0;
         sb.add_gemv(G, eb);
       }
@@ -659,6 +669,12 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
   h->l_pv = reduced(h->d_p, h->d_v, h->d_rt, V_DOT);
   h->l_st = reduced(h->d_s, h->d_tv, h->d_s, V_DOT | V_DOT2);
   h->l_zv = reduced(h->d_zh, h->d_v, nullptr, 0);
+  if (h->opt.inner_prec == 1) {
+    h->l_lp = reduced(h->d_p, h->d_mp, nullptr, 0, true);
+    h->l_ls = reduced(h->d_s, h->d_ms, nullptr, 0, true);
+    h->l_pvh = reduced(h->d_mp, h->d_v, h->d_rt, V_DOT);
+    h->l_sth = reduced(h->d_ms, h->d_tv, h->d_s, V_DOT | V_DOT2);
+  }
   h->W1 = h->l_pv.nwg;
 }
 
@@ -820,6 +836,7 @@ int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::v
     return DDPS_OK;
   }
   const int W2 = vec_grid(m);
+  const bool prec = h->opt.inner_prec == 1;
   double* S0 = h->d_sums;
   double* S1 = S0 + 2 * kMaxRhs;
   double* S2 = S1 + 2 * kMaxRhs;
@@ -841,14 +858,17 @@ int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::v
     int last = std::min(maxit, it + batch - 1);
     for (; it <= last; ++it) {
       const int32_t* stop = &h->d_state->status[it & 1][0];
-      run_launch(h, h->l_pv, R, m, m, h->d_rt, h->d_part_buf, stop, TK_RSPMV);
+      // right preconditioning: v = G^ M^{-1} p, t = G^ M^{-1} s, x += a M^{-1} p + w M^{-1} s
+      if (prec) run_launch(h, h->l_lp, R, m, m, nullptr, nullptr, stop, TK_RSPMV);
+      run_launch(h, prec ? h->l_pvh : h->l_pv, R, m, m, h->d_rt, h->d_part_buf, stop, TK_RSPMV);
       reduce2(R, h->W1, h->d_part_buf, S1, stop, s);
       bicg_s(R, it, m, S1, h->d_state, h->d_r, h->d_v, h->d_s, h->d_part_buf, W2, s);
       reduce2(R, W2, h->d_part_buf, S2, stop, s);
-      run_launch(h, h->l_st, R, m, m, h->d_s, h->d_part_buf, stop, TK_RSPMV);
+      if (prec) run_launch(h, h->l_ls, R, m, m, nullptr, nullptr, stop, TK_RSPMV);
+      run_launch(h, prec ? h->l_sth : h->l_st, R, m, m, h->d_s, h->d_part_buf, stop, TK_RSPMV);
       reduce2(R, h->W1, h->d_part_buf, S3, stop, s);
       bicg_xr(R, it, m, tol, S1, S2, S3, h->d_state, h->d_zh, h->d_p, h->d_s, h->d_tv, h->d_r, h->d_rt,
-              h->d_part_buf, W2, s);
+              h->d_part_buf, W2, s, prec ? h->d_mp : nullptr, prec ? h->d_ms : nullptr);
       reduce2(R, W2, h->d_part_buf, S4, stop, s);
       bicg_p(R, it, maxit, m, tol, S1, S2, S3, S4, h->d_state, h->d_r, h->d_p, h->d_v, W2, s);
     }
@@ -997,6 +1017,7 @@ void ddps_default_options(ddps_options* o) {
   o->stream = nullptr;
   o->factor_streams = 0;
   o->factor_graph = 0;
+  o->inner_prec = 0;
 }
 
 const char* ddps_status_string(int s) {
@@ -1061,7 +1082,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   }
   const ddps_options& o = h->opt;
   if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
-      o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0)) {
+      o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
+      o.inner_prec > 1) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1150,7 +1172,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   need += (size_t)p * h->scr_per_block * h->elt;
   need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
   need += (size_t)h->Np * R * 8 * 2 + (size_t)h->Np * 8;
-  need += (size_t)m * R * 8 * 9;
+  need += (size_t)m * R * 8 * 11;
   need += (size_t)n * R * 8 * 10;
   need += (size_t)Wmax * R * 4 * 8;
   size_t budget = o.mem_budget;
@@ -1179,7 +1201,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   const int64_t mR = std::max<int64_t>(m, 1) * R;
   if ((rc = h->alloc(h->d_gh, mR)) || (rc = h->alloc(h->d_zh, mR)) || (rc = h->alloc(h->d_r, mR)) ||
       (rc = h->alloc(h->d_rt, mR)) || (rc = h->alloc(h->d_p, mR)) || (rc = h->alloc(h->d_v, mR)) ||
-      (rc = h->alloc(h->d_s, mR)) || (rc = h->alloc(h->d_tv, mR)) || (rc = h->alloc(h->d_guess, mR)))
+      (rc = h->alloc(h->d_s, mR)) || (rc = h->alloc(h->d_tv, mR)) || (rc = h->alloc(h->d_guess, mR)) ||
+      (rc = h->alloc(h->d_mp, mR)) || (rc = h->alloc(h->d_ms, mR)))
     return fail(rc);
   const int64_t nR = n * R;
   if ((rc = h->alloc(h->d_fo, nR)) || (rc = h->alloc(h->d_xo, nR)) || (rc = h->alloc(h->d_ro, nR)) ||
@@ -1193,7 +1216,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     return fail(rc);
   // zero every vector buffer once (unused RHS columns stay finite)
   for (double* q : {h->d_ypad, h->d_vpad}) fill_f64(q, h->Np * R, 0.0, s);
-  for (double* q : {h->d_gh, h->d_zh, h->d_r, h->d_rt, h->d_p, h->d_v, h->d_s, h->d_tv, h->d_guess})
+  for (double* q : {h->d_gh, h->d_zh, h->d_r, h->d_rt, h->d_p, h->d_v, h->d_s, h->d_tv, h->d_guess, h->d_mp, h->d_ms})
     fill_f64(q, mR, 0.0, s);
   for (double* q : {h->d_fo, h->d_xo, h->d_ro, h->d_z, h->d_rto, h->d_po, h->d_vo, h->d_ph, h->d_sh, h->d_to})
     fill_f64(q, nR, 0.0, s);

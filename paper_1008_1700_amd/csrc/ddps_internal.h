@@ -180,9 +180,11 @@ void bicg_init(int R, int64_t m, int use_guess, const double* gh, double* x, con
 void bicg_init_state(int R, int k, double tol, const double* sums, KState* st, hipStream_t s);
 void bicg_s(int R, int it, int64_t m, const double* s1, KState* st, const double* r, const double* v,
             double* sv, double* part, int W, hipStream_t s);
+// px, sx (may be null = p, sv): directions added to x, M^{-1}p and M^{-1}s when preconditioned
 void bicg_xr(int R, int it, int64_t m, double tol, const double* s1, const double* s2, const double* s3,
              KState* st, double* x, const double* p, const double* sv, const double* t, double* r,
-             const double* rt, double* part, int W, hipStream_t s);
+             const double* rt, double* part, int W, hipStream_t s, const double* px = nullptr,
+             const double* sx = nullptr);
 void bicg_p(int R, int it, int maxit, int64_t m, double tol, const double* s1, const double* s2,
             const double* s3, const double* s4, KState* st, const double* r, double* p, const double* v,
             int W, hipStream_t s);

@@ -223,7 +223,9 @@ __global__ __launch_bounds__(256) void k_bicg_xr(int it, int64_t m, double tol, 
                                                  KState* __restrict__ st, double* __restrict__ x,
                                                  const double* __restrict__ p, const double* __restrict__ s,
                                                  const double* __restrict__ t, double* __restrict__ r,
-                                                 const double* __restrict__ rt, double* __restrict__ part) {
+                                                 const double* __restrict__ rt, double* __restrict__ part,
+                                                 const double* __restrict__ px, const double* __restrict__ sx) {
+  // px, sx: the directions added to x (M^{-1}p, M^{-1}s when preconditioned, else p, s)
   __shared__ double sh[4][R][2];
   double al[R], om[R];
   bool run[R], half[R];
@@ -248,10 +250,10 @@ __global__ __launch_bounds__(256) void k_bicg_xr(int it, int64_t m, double tol, 
     for (int j = 0; j < R; ++j) {
       const int64_t k = i + j * m;
       if (half[j]) {
-        x[k] += al[j] * p[k];
+        x[k] += al[j] * px[k];
       } else if (run[j]) {
         const double sv = s[k];
-        x[k] += al[j] * p[k] + om[j] * sv;
+        x[k] += al[j] * px[k] + om[j] * sx[k];
         const double rv = sv - om[j] * t[k];
         r[k] = rv;
         acc[j][0] += rv * rv;
@@ -550,8 +552,9 @@ void bicg_s(int R, int it, int64_t m, const double* s1, KState* st, const double
 }
 void bicg_xr(int R, int it, int64_t m, double tol, const double* s1, const double* s2, const double* s3,
              KState* st, double* x, const double* p, const double* sv, const double* t, double* r,
-             const double* rt, double* part, int W, hipStream_t s) {
-  DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_bicg_xr<RR>, dim3(W), dim3(256), 0, s, it, m, tol, s1, s2, s3, st, x, p, sv, t, r, rt, part));
+             const double* rt, double* part, int W, hipStream_t s, const double* px, const double* sx) {
+  DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_bicg_xr<RR>, dim3(W), dim3(256), 0, s, it, m, tol, s1, s2, s3, st, x, p, sv, t, r, rt, part,
+                                        px ? px : p, sx ? sx : sv));
 }
 void bicg_p(int R, int it, int maxit, int64_t m, double tol, const double* s1, const double* s2,
             const double* s3, const double* s4, KState* st, const double* r, double* p, const double* v,

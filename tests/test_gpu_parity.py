@@ -130,6 +130,36 @@ def test_c1_preconditioner(c1, c1_solver, c1_oracle):
     assert 5 <= its[0] <= 100
 
 
+def test_c1_locally_preconditioned_inner_solve(c1, c1_solver, c1_oracle):
+    """inner_prec=1 (right preconditioning of the reduced BiCGStab by
+    I - N, N the interface-local part of G(c,c)): the same preconditioner
+    application z = P^{-1} y as the exact reduced solve, in fewer inner
+    iterations, matching the oracle's iterate count."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    S = make_solver(c1, inner_tol=1e-14, max_rhs=4, inner_prec=1)
+    try:
+        S.factor()
+        Y = np.random.default_rng(5).standard_normal((2, c1["A"].n))
+        Z = torch.empty(2, c1["A"].n, dtype=torch.float64, device="cuda")
+        gh = torch.empty(2 * 384, dtype=torch.float64, device="cuda")
+        zh = torch.empty(2 * 384, dtype=torch.float64, device="cuda")
+        its = ddps.ddps_apply_preconditioner(S.h, 2, torch.from_numpy(Y).cuda(), Z, gh, zh)
+        z0 = torch.empty(c1["A"].n, dtype=torch.float64, device="cuda")
+        its0 = ddps.ddps_apply_preconditioner(c1_solver.h, 1, dev_vec(Y[0]), z0)
+        for j in range(2):
+            ze, d = c1_oracle.apply(Y[j], reduced="dense")
+            _, dl = c1_oracle.apply(Y[j], reduced="bicgstab", inner_tol=1e-14, inner_prec="local")
+            assert relerr(host(zh)[j * 384:(j + 1) * 384], d["zhat"]) <= 1e-11
+            assert relerr(host(Z)[j], ze) <= 1e-11
+            print(f"rhs {j}: local-preconditioned {its[j]} iterations, oracle {dl['inner'].iters}")
+            assert abs(its[j] - dl["inner"].iters) <= 1.0
+        print(f"unpreconditioned: {its0[0]} iterations")
+        assert its[0] < its0[0]
+    finally:
+        S.close()
+
+
 def test_c1_solve_matches_oracle(c1, c1_solver):
     from oracle import ddps_oracle as O
     A = c1["A"]

@@ -220,3 +220,42 @@ def test_planted_strict_drop_test_is_caught(monkeypatch):
     A = d["A"]
     P = O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"], delta=1.0)
     assert P.m != 0
+
+
+def test_local_part_of_reduced_matrix():
+    # N is a restriction of G(c,c): with one interface (p = 2) it is all of
+    # it, and in general N and the rest split G^ - I entry by entry (each
+    # entry of G(c,c) is either local or not).
+    from oracle import ddps_oracle as O
+    d = configs.small_banded(2, [150, 170], 6, 3)
+    A = d["A"]
+    P = O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"])
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal(P.m)
+    assert np.allclose(P.local_matvec(z), P.ghat_matvec(z) - z, rtol=1e-14, atol=1e-14)
+    d = configs.small_banded(4, [150, 170, 160, 140], 6, 3)
+    A = d["A"]
+    P = O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"])
+    Gm = P.ghat_dense() - np.eye(P.m)
+    Nm = np.column_stack([P.local_matvec(e) for e in np.eye(P.m)])
+    on = Nm != 0
+    assert np.array_equal(Nm[on], Gm[on])                  # N copies entries of G(c,c)
+    assert 0 < on.sum() < (Gm != 0).sum()                   # and leaves the cross-interface ones
+    # rows and columns of one interface only: N is block diagonal over interfaces
+    part = d["part_ptr"]
+    bnd = np.asarray(part[1:-1])
+    iface = np.abs(P.c[:, None] - bnd[None, :]).argmin(axis=1)
+    assert np.all(iface[np.nonzero(on)[0]] == iface[np.nonzero(on)[1]])
+
+
+def test_locally_preconditioned_inner_solve_gives_same_solution():
+    from oracle import ddps_oracle as O
+    d = configs.small_banded(5, [150, 170, 160, 140, 155], 6, 8)
+    A = d["A"]
+    P = O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"])
+    y = np.random.default_rng(1).standard_normal(A.n)
+    z0, r0 = P.apply(y, reduced="dense")
+    z1, r1 = P.apply(y, reduced="bicgstab", inner_tol=1e-13, inner_prec="local")
+    z2, r2 = P.apply(y, reduced="bicgstab", inner_tol=1e-13)
+    assert np.allclose(z1, z0, rtol=1e-10, atol=1e-11)
+    assert r1["inner"].iters <= r2["inner"].iters

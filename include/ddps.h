@@ -215,14 +215,19 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
  * the factorisation once as a HIP graph and replay it, tile_policy = 0 for
  * 128 x 128 GEMM tiles where every problem of a launch allows them, 1 for
  * 64 x 64 tiles only, 2 for 256 x 128 tiles where every problem allows them
- * (bf16 arithmetic; otherwise as 0).  Rebuilds the launch schedules; call before
- * ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM, DDPS_E_HIP. */
+ * (bf16 arithmetic; otherwise as 0), 3 for a tile chosen per launch by
+ * ddps_autotune (as 0 until the autotuner has run).  Rebuilds the launch
+ * schedules; call before ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM,
+ * DDPS_E_HIP. */
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
 /* Autotuner of the execution form: times ddps_factor on the device for
  * stream groups {1, 2, 4, 8} (at most p) and every tile policy (2 only for
- * the bf16 dtypes), keeps the
- * fastest, and records it in the JSON file cache_path (may be NULL) under a
+ * the bf16 dtypes); then, for the best group count, times every GEMM launch
+ * of the factorisation under each policy and builds policy 3 from the
+ * fastest tile of each launch.  It keeps the fastest form, and records it
+ * (policy 3 is re-derived on a cache hit) in the JSON file cache_path (may be
+ * NULL) under a
  * key made of the GPU architecture, factor dtype, tile size t, p and the
  * largest tile-row count; a later call with the same key takes the cached
  * choice without timing.  Host outputs (may be NULL): chosen streams, tile

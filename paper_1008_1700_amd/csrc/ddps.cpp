@@ -122,7 +122,10 @@ struct ddps_ctx {
   std::vector<Launch> sch_fwd, sch_bwd, sch_retr;
   int groups = 1;          // stream groups of the factor schedule
   int tile_policy = 0;     // 0: 128 x 128 GEMM tiles where every problem allows, 1: 64 x 64 only,
-                           // 2: 256 x 128 (bf16 arithmetic) where every problem allows
+                           // 2: 256 x 128 (bf16 arithmetic) where every problem allows,
+                           // 3: per launch, from mode_choice
+  std::vector<int8_t> mode_choice;  // policy 3: requested tile mode of each factor GEMM launch, in order
+  int mode_cursor = 0;              // next factor GEMM launch while the schedules are built
   bool use_graph = false;  // capture ddps_factor once as a HIP graph, then replay it
   hipStream_t fstream = nullptr;          // internal stream of the factorisation
   std::vector<hipStream_t> gstream;       // one per group beyond the first
@@ -279,12 +282,18 @@ struct ScheduleBuilder {
     flops = bytes = 0;
     off = k == LK_GEMM ? (int64_t)gemm.size() : k == LK_PANEL ? (int64_t)panel.size() : (int64_t)gemv.size();
   }
-  // GEMM launches: 128 x 128 tiles when every problem is at least that
-  // large, else 64 x 64; assigns each problem its first workgroup.
+  // Tile mode the policy asks for (0: 64 x 64, 1: 128 x 128, 2: 256 x 128).
+  int requested_mode() const {
+    if (h->tile_policy == 3)
+      return h->mode_cursor < (int)h->mode_choice.size() ? h->mode_choice[h->mode_cursor] : 1;
+    return h->tile_policy == 1 ? 0 : (h->tile_policy == 2 && h->gdt >= 2) ? 2 : 1;
+  }
+  // GEMM launches: the requested tile, narrowed to the largest one every
+  // problem of the launch fills (256 x 128 only for bf16 arithmetic, 128 x 128,
+  // else 64 x 64); assigns each problem its first workgroup.
   int finish_gemm() {
-    // the largest tile every problem of the launch fills: 256 x 128 (bf16
-    // arithmetic, policy 2), 128 x 128, else 64 x 64
-    int mode = h->tile_policy == 1 ? 0 : (h->tile_policy == 2 && h->gdt >= 2) ? 2 : 1;
+    int mode = requested_mode();
+    if (mode == 2 && h->gdt < 2) mode = 1;
     for (size_t q = (size_t)off; q < gemm.size(); ++q) {
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
       else if (mode == 2 && gemm[q].M < 256) mode = 1;
@@ -305,7 +314,10 @@ struct ScheduleBuilder {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
                                                                               : (int64_t)gemv.size()) - off;
     const int mode = kind == LK_GEMM ? finish_gemm() : 0;
-    if (cnt > 0 && nwg > 0) out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode});
+    if (cnt > 0 && nwg > 0) {
+      out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode});
+      if (kind == LK_GEMM) ++h->mode_cursor;
+    }
   }
   Launch end_one() {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
@@ -781,6 +793,7 @@ int build_schedules(ddps_ctx* h) {
   }
   ScheduleBuilder sb;
   sb.h = h;
+  h->mode_cursor = 0;
   h->sch_group.assign(G, {});
   for (int g = 0; g < G; ++g) {
     std::vector<int> mem;
@@ -1762,7 +1775,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
 }
 
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
-  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 2) return DDPS_E_ARG;
+  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 3) return DDPS_E_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipStreamSynchronize(h->fstream));
   h->groups = streams > 0 ? streams : default_groups(h);
@@ -1845,13 +1858,72 @@ void cache_store(const char* path, const std::string& key, int streams, int poli
 
 }  // namespace
 
+namespace {
+// Durations (ms) of the factor GEMM launches of one ddps_factor, in order.
+int time_gemm_launches(ddps_ctx* h, std::vector<float>& out) {
+  int rc;
+  auto drain = [&]() {
+    for (auto& r : h->tim[TK_GEMM]) {
+      h->ev_pool.push_back(r.a);
+      h->ev_pool.push_back(r.b);
+    }
+    h->tim[TK_GEMM].clear();
+  };
+  HIPCHK(hipDeviceSynchronize());
+  drain();
+  const bool was = h->tim_on[TK_GEMM];
+  h->tim_on[TK_GEMM] = true;
+  rc = ddps_factor(h);
+  h->tim_on[TK_GEMM] = was;
+  if (rc) return rc;
+  HIPCHK(hipDeviceSynchronize());
+  out.clear();
+  for (auto& r : h->tim[TK_GEMM]) {
+    float e = 0;
+    HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
+    out.push_back(e);
+  }
+  drain();
+  return DDPS_OK;
+}
+
+// Policy 3 for `groups` stream groups: time every factor GEMM launch under
+// each fixed policy, keep per launch the tile of the fastest, and time the
+// resulting schedule (*ms).  Leaves the handle factored with policy 3.
+int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
+  static const int8_t mode_of_policy[3] = {1, 0, 2};
+  const int nq = h->gdt >= 2 ? 3 : 2;
+  std::vector<std::vector<float>> t(nq);
+  int rc;
+  for (int q = 0; q < nq; ++q) {
+    if ((rc = ddps_set_execution(h, groups, 0, q))) return rc;
+    if ((rc = ddps_factor(h))) return rc;   // warm-up
+    if ((rc = time_gemm_launches(h, t[q]))) return rc;
+    if (t[q].size() != t[0].size()) return DDPS_E_STATE;
+  }
+  h->mode_choice.assign(t[0].size(), 1);
+  for (size_t i = 0; i < t[0].size(); ++i) {
+    int best = 0;
+    for (int q = 1; q < nq; ++q)
+      if (t[q][i] < t[best][i]) best = q;
+    h->mode_choice[i] = mode_of_policy[best];
+  }
+  if ((rc = ddps_set_execution(h, groups, 0, 3))) return rc;
+  if ((rc = ddps_factor(h))) return rc;   // warm-up
+  if ((rc = ddps_factor(h))) return rc;
+  *ms = h->t_factor_ms;
+  return DDPS_OK;
+}
+}  // namespace
+
 int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy, double* factor_ms) {
   if (!h) return DDPS_E_ARG;
   const std::string key = tune_key(h);
   int bs = 0, bq = 0;
   double bms = 0;
   int rc;
-  if (!cache_lookup(cache_path, key, &bs, &bq, &bms)) {
+  const bool hit = cache_lookup(cache_path, key, &bs, &bq, &bms);
+  if (!hit) {
     bms = 1e300;
     for (int q = 0; q <= (h->gdt >= 2 ? 2 : 1); ++q)
       for (int g : {1, 2, 4, 8}) {
@@ -1865,8 +1937,19 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
           bq = q;
         }
       }
-    cache_store(cache_path, key, bs, bq, bms);
   }
+  if (!hit || bq == 3) {
+    // per-launch tile choice for the chosen group count: every factor GEMM
+    // launch is timed under each policy (same launch sequence), and takes
+    // the tile of the policy under which it ran fastest
+    double ms3 = 0;
+    if ((rc = tune_launch_modes(h, bs, &ms3))) return rc;
+    if (hit || ms3 < bms) {
+      bq = 3;
+      if (!hit) bms = ms3;
+    }
+  }
+  if (!hit) cache_store(cache_path, key, bs, bq, bms);
   const int graph = h->use_graph ? 1 : 0;
   if ((rc = ddps_set_execution(h, bs, graph, bq))) return rc;
   if ((rc = ddps_factor(h))) return rc;

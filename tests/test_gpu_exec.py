@@ -92,7 +92,7 @@ def test_autotune_and_cache(tmp_path):
     S = make_solver(d, inner_tol=1e-13)
     try:
         r1 = ddps.ddps_autotune(S.h, str(cache))
-        assert r1["streams"] in (1, 2, 4) and r1["tile_policy"] in (0, 1) and r1["factor_ms"] > 0
+        assert r1["streams"] in (1, 2, 4) and r1["tile_policy"] in (0, 1, 3) and r1["factor_ms"] > 0
         x, info = _solve(S, d)
         assert info.relres_inf <= 1e-12
         data = json.loads(cache.read_text())
@@ -123,5 +123,15 @@ def test_bf16x3_tile_policies_agree():
             xs[policy] = x
         finally:
             S.close()
+    # the autotuner's form, possibly policy 3 (a tile chosen per launch)
+    S = make_solver(d, dtype="bf16x3", inner_tol=1e-8)
+    try:
+        r = ddps.ddps_autotune(S.h)
+        assert r["tile_policy"] in (0, 1, 2, 3)
+        x, info = _solve(S, d, tol=1e-11)
+        assert info.relres_inf <= 1e-11
+        xs[3] = x
+    finally:
+        S.close()
     assert relerr(xs[2], d["x_star"]) <= 1e-9
-    assert relerr(xs[2], xs[0]) <= 1e-10 and relerr(xs[1], xs[0]) <= 1e-10
+    assert all(relerr(xs[q], xs[0]) <= 1e-10 for q in (1, 2, 3))

@@ -57,7 +57,7 @@ def build_workload(name):
 
 
 def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None, exec_form=None,
-             inner_prec=0):
+             inner_prec=0, tune_cache=None):
     import torch
     from paper_1008_1700_amd import ddps
     A = d["A"]
@@ -73,7 +73,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         x = torch.zeros(k, A.n, dtype=torch.float64, device="cuda")
     val = S.val
     if exec_form is None:
-        tune = ddps.ddps_autotune(S.h)        # execution form (stream groups, tile policy), untimed
+        tune = ddps.ddps_autotune(S.h, tune_cache)   # execution form (stream groups, tiles), untimed
     else:
         ddps.ddps_set_execution(S.h, exec_form[0], False, exec_form[1])
         tune = dict(streams=exec_form[0], tile_policy=exec_form[1], factor_ms=None)
@@ -87,9 +87,6 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    ddps.ddps_timing_read(S.h, timing_kind)            # clear
-    ddps.ddps_timing_enable(S.h, timing_kind, True)
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -97,10 +94,18 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         infos.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ddps.ddps_timing_enable(S.h, timing_kind, False)
-    tim = ddps.ddps_timing_read(S.h, timing_kind)
     rc, info = infos[-1]
     xs = x.cpu().numpy()
+    # one more (untimed) step with every factor GEMM launch timed by HIP events
+    # on its stream; while they are timed the stream groups run one after
+    # another, so each interval holds its own kernel only (the timed steps
+    # above run the groups concurrently and carry no per-launch events)
+    ddps.ddps_timing_read(S.h, timing_kind)            # clear
+    ddps.ddps_timing_enable(S.h, timing_kind, True)
+    step()
+    torch.cuda.synchronize()
+    ddps.ddps_timing_enable(S.h, timing_kind, False)
+    tim = ddps.ddps_timing_read(S.h, timing_kind)
     # one more (untimed) step with the solve-phase GEMV launches timed
     gemv = dict(launches=0, ms=0.0, bytes=0.0, per_kind={})
     for kind in ("sweep", "reduced", "retrieval"):
@@ -138,9 +143,10 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         applications=info.applications,
         relres_inf=float(np.max(np.max(np.abs(r), axis=0) / nf)),
         relerr_xstar=float(np.max(np.linalg.norm(X - xst, axis=0) / np.linalg.norm(xst, axis=0))),
-        kernel=dict(kind=timing_kind, launches_per_step=tim["launches"] / steps,
-                    ms_per_step=tim["ms"] / steps, flops_per_step=tim["flops"] / steps,
-                    bytes_per_step=tim["bytes"] / steps),
+        kernel=dict(kind=timing_kind, launches_per_step=tim["launches"], ms_per_step=tim["ms"],
+                    flops_per_step=tim["flops"], bytes_per_step=tim["bytes"],
+                    timing="one untimed step after the timed steps, per-launch HIP events, "
+                           "stream groups one after another"),
         mem_gb=ddps.ddps_memory(S.h) / 1e9,
         inner_tol=inner_tol, gemv=gemv,
         exec=dict(tune, graph_ms_per_step=graph_ms),
@@ -254,7 +260,7 @@ def run_c4(args):
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
     S = ddps.Solver(A1, part, dtype=args.mode, inner_tol=itol, outer="refine", guess=True,
                     inner_prec=args.inner_prec if args.mode != "f64" else 0)
-    tune = ddps.ddps_autotune(S.h)
+    tune = ddps.ddps_autotune(S.h, args.tune_cache)
     log(f"c4: n={A1.n} p={p} mode={args.mode} exec={tune}")
     t0 = time.perf_counter()
     out = guess.run_sequence(S, lambda st: configs.c4_step_values(st, kinds, nx), steps=args.c4_steps,
@@ -319,6 +325,8 @@ def main():
                     help="inner BiCGStab preconditioner of the timed mode (0 none, 1 interface-local)")
     ap.add_argument("--graph-steps", type=int, default=2, help="extra steps timed with the factor graph")
     ap.add_argument("--exec", default=None, help="fixed execution form 'streams,tile_policy' instead of the autotuner")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of the autotuner's choices (reused when present, so counter runs repeat the form)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the calibration copy (3 x 1 GiB)")
     ap.add_argument("--c4-steps", type=int, default=300)
     ap.add_argument("--c4-train", type=int, default=200)
@@ -343,14 +351,14 @@ def main():
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
     iprec = args.inner_prec if args.mode != "f64" else 0
     res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps,
-                   exec_form=exec_form, inner_prec=iprec)
+                   exec_form=exec_form, inner_prec=iprec, tune_cache=args.tune_cache)
     log(f"{args.mode}: {json.dumps(res)}")
     base = None
     if not args.no_baseline and args.mode != "f64":
         from paper_1008_1700_amd import ddps
         try:
             base = run_mode(d, "f64", args.steps, args.warmup, args.tol, args.inner_tol_f64,
-                            graph_steps=args.graph_steps, exec_form=exec_form)
+                            graph_steps=args.graph_steps, exec_form=exec_form, tune_cache=args.tune_cache)
         except ddps.DDPSError as e:
             # FP64 factors and spikes beyond the device memory: the paper's failure F1
             base = dict(mode="f64", status=str(e), ms_per_step=None)
@@ -359,12 +367,11 @@ def main():
     kms = k["ms_per_step"]
     peak = PEAKS[args.mode]
     # achieved: the band-LU + spike algorithmic flops of stages 2 and 4 per
-    # step over the summed durations of the grouped GEMM launches (HIP events
-    # on each launch's stream, timed steps).  With stream groups launches of
-    # different groups overlap, so the summed durations overstate the GEMM's
-    # own time and the rate is a lower bound.  mfma_rate counts the products
-    # the launches execute (tile-granular triangles; three bf16 products per
-    # split product).
+    # step over the summed durations of the grouped GEMM launches of one
+    # factorisation (HIP events on each launch's stream, in the GEMM-timed
+    # step whose stream groups run one after another).  mfma_rate counts the
+    # products the launches execute (tile-granular triangles; three bf16
+    # products per split product).
     alg = band_lu_spike_flops(d)
     achieved = alg / (kms * 1e-3) if kms > 0 else 0.0
     split = 3.0 if args.mode == "bf16x3" else 1.0
@@ -373,6 +380,7 @@ def main():
                 frac=achieved / peak, traffic=traffic,
                 kernel="k_gemm_bf16 / k_gemm_std (grouped GEMM of stages 2 and 4)",
                 launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms,
+                stream_groups=res["exec"]["streams"], launch_timing=k.get("timing"),
                 avg_launch_us=kms * 1e3 / max(k["launches_per_step"], 1),
                 algorithmic_flops_per_step=alg,
                 mfma_rate=k["flops_per_step"] * split / (kms * 1e-3) / 1e12 if kms > 0 else None,

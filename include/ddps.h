@@ -216,14 +216,17 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
  * 128 x 128 GEMM tiles where every problem of a launch allows them, 1 for
  * 64 x 64 tiles only, 2 for 256 x 128 tiles where every problem allows them
  * (bf16 arithmetic; otherwise as 0), 3 for a tile chosen per launch by
- * ddps_autotune (as 0 until the autotuner has run).  Rebuilds the launch
+ * ddps_autotune (as 0 until the autotuner has run), 4 for 128 x 128 tiles
+ * with 64-deep K chunks where every problem allows them (bf16 arithmetic;
+ * otherwise as 0).  Rebuilds the launch
  * schedules; call before ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM,
  * DDPS_E_HIP. */
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
 /* Autotuner of the execution form: times ddps_factor on the device for
  * stream groups {1, 2, 4, 8} (at most p) and every tile policy (2 only for
- * the bf16 dtypes); then, for the best group count, times every GEMM launch
+ * the bf16 dtypes) and takes the fewest groups within 3% of the fastest form;
+ * then, for that group count, times every GEMM launch
  * of the factorisation under each policy and builds policy 3 from the
  * fastest tile of each launch.  It keeps the fastest form, and records it
  * (policy 3 is re-derived on a cache hit) in the JSON file cache_path (may be
@@ -237,8 +240,10 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
                   double* factor_ms);
 
 /* Per-kernel timing for roofline reporting.  ddps_timing_enable(h, kind, 1)
- * records HIP events around every launch of that kernel kind on the handle's
- * stream; ddps_timing_read reports launches, summed device milliseconds and
+ * records HIP events around every launch of that kernel kind on the stream it
+ * is launched on (while kind 0 or 1 is timed, the stream groups of
+ * ddps_factor run one after another, so that the intervals do not overlap);
+ * ddps_timing_read reports launches, summed device milliseconds and
  * the algorithmic flops and bytes of those launches (host pointers), then
  * clears the counters.  kind: 0 = grouped GEMM (factor and spikes),
  * 1 = diagonal-tile LU, 2 = block-sweep GEMV, 3 = reduced-matrix product,

@@ -286,6 +286,7 @@ struct ScheduleBuilder {
   int requested_mode() const {
     if (h->tile_policy == 3)
       return h->mode_cursor < (int)h->mode_choice.size() ? h->mode_choice[h->mode_cursor] : 1;
+    if (h->tile_policy == 4) return 3;
     return h->tile_policy == 1 ? 0 : (h->tile_policy == 2 && h->gdt >= 2) ? 2 : 1;
   }
   // GEMM launches: the requested tile, narrowed to the largest one every
@@ -293,7 +294,7 @@ struct ScheduleBuilder {
   // else 64 x 64); assigns each problem its first workgroup.
   int finish_gemm() {
     int mode = requested_mode();
-    if (mode == 2 && h->gdt < 2) mode = 1;
+    if (mode >= 2 && h->gdt < 2) mode = 1;
     for (size_t q = (size_t)off; q < gemm.size(); ++q) {
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
       else if (mode == 2 && gemm[q].M < 256) mode = 1;
@@ -756,8 +757,13 @@ int enqueue_factor(ddps_ctx* h) {
   int rc = do_scatter(h, f);
   if (rc) return rc;
   const int G = (int)h->sch_group.size();
-  if (G <= 1) {
-    if (G == 1 && (rc = run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f))) return rc;
+  // with per-launch timing of the factor kernels the groups run one after
+  // another on the factor stream, so that each launch's event interval holds
+  // its own kernel only (same launches, no overlap between groups)
+  const bool serial = h->tim_on[TK_GEMM] || h->tim_on[TK_PANEL];
+  if (G <= 1 || serial) {
+    for (int g = 0; g < G; ++g)
+      if ((rc = run_schedule(h, h->sch_group[g], 1, 0, 0, TK_GEMM, f))) return rc;
     if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
     HIPCHK(hipGetLastError());
     return DDPS_OK;
@@ -1775,7 +1781,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
 }
 
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
-  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 3) return DDPS_E_ARG;
+  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 4) return DDPS_E_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipStreamSynchronize(h->fstream));
   h->groups = streams > 0 ? streams : default_groups(h);
@@ -1804,8 +1810,11 @@ std::string tune_key(ddps_ctx* h) {
 }
 
 // The cache is a flat JSON object {"key": {"streams": s, "tile_policy": q,
-// "factor_ms": ms}, ...} written and read by this file only.
-bool cache_lookup(const char* path, const std::string& key, int* streams, int* policy, double* ms) {
+// "factor_ms": ms, "modes": "..."}, ...}, one entry per line, written and
+// read by this file only; "modes" (policy 3) holds the tile mode of each
+// factor GEMM launch as one digit.
+bool cache_lookup(const char* path, const std::string& key, int* streams, int* policy, double* ms,
+                  std::string* modes) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
@@ -1825,27 +1834,44 @@ bool cache_lookup(const char* path, const std::string& key, int* streams, int* p
   *streams = s2;
   *policy = q2;
   *ms = m2;
+  modes->clear();
+  const size_t end = txt.find('}', br);
+  const std::string tag = "\"modes\": \"";
+  const size_t mp = txt.find(tag, br);
+  if (mp != std::string::npos && mp < end)
+    for (size_t i = mp + tag.size(); i < txt.size() && txt[i] >= '0' && txt[i] <= '3'; ++i) modes->push_back(txt[i]);
   return true;
 }
 
-void cache_store(const char* path, const std::string& key, int streams, int policy, double ms) {
+void cache_store(const char* path, const std::string& key, int streams, int policy, double ms,
+                 const std::string& modes) {
   if (!path) return;
   std::vector<std::string> entries;
   if (FILE* f = std::fopen(path, "r")) {
-    char line[1024];
-    while (std::fgets(line, sizeof(line), f)) {
-      std::string l(line);
+    std::string txt;
+    char b[4096];
+    size_t nr;
+    while ((nr = std::fread(b, 1, sizeof(b), f)) > 0) txt.append(b, nr);
+    std::fclose(f);
+    size_t pos = 0;
+    while (pos < txt.size()) {
+      size_t nl = txt.find('\n', pos);
+      if (nl == std::string::npos) nl = txt.size();
+      std::string l = txt.substr(pos, nl - pos);
+      pos = nl + 1;
       if (l.find("\"streams\"") != std::string::npos && l.find("\"" + key + "\"") == std::string::npos) {
         while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
         entries.push_back(l);
       }
     }
-    std::fclose(f);
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": {\"streams\": %d, \"tile_policy\": %d, \"factor_ms\": %.3f}", key.c_str(),
+  std::snprintf(buf, sizeof(buf), "  \"%s\": {\"streams\": %d, \"tile_policy\": %d, \"factor_ms\": %.3f", key.c_str(),
                 streams, policy, ms);
-  entries.push_back(buf);
+  std::string e = buf;
+  if (policy == 3 && !modes.empty()) e += ", \"modes\": \"" + modes + "\"";
+  e += "}";
+  entries.push_back(e);
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return;
@@ -1891,15 +1917,20 @@ int time_gemm_launches(ddps_ctx* h, std::vector<float>& out) {
 // each fixed policy, keep per launch the tile of the fastest, and time the
 // resulting schedule (*ms).  Leaves the handle factored with policy 3.
 int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
-  static const int8_t mode_of_policy[3] = {1, 0, 2};
-  const int nq = h->gdt >= 2 ? 3 : 2;
+  // fixed policies 0, 1, 2 and 4 ask for tile modes 1, 0, 2 and 3
+  static const int8_t mode_of_policy[4] = {1, 0, 2, 3};
+  static const int policy_of[4] = {0, 1, 2, 4};
+  const int nq = h->gdt >= 2 ? 4 : 2;
   std::vector<std::vector<float>> t(nq);
   int rc;
+  std::vector<float> t2;
   for (int q = 0; q < nq; ++q) {
-    if ((rc = ddps_set_execution(h, groups, 0, q))) return rc;
+    if ((rc = ddps_set_execution(h, groups, 0, policy_of[q]))) return rc;
     if ((rc = ddps_factor(h))) return rc;   // warm-up
     if ((rc = time_gemm_launches(h, t[q]))) return rc;
-    if (t[q].size() != t[0].size()) return DDPS_E_STATE;
+    if ((rc = time_gemm_launches(h, t2))) return rc;   // per launch, the faster of two runs
+    if (t[q].size() != t[0].size() || t2.size() != t[q].size()) return DDPS_E_STATE;
+    for (size_t i = 0; i < t2.size(); ++i) t[q][i] = std::min(t[q][i], t2[i]);
   }
   h->mode_choice.assign(t[0].size(), 1);
   for (size_t i = 0; i < t[0].size(); ++i) {
@@ -1922,23 +1953,41 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
   int bs = 0, bq = 0;
   double bms = 0;
   int rc;
-  const bool hit = cache_lookup(cache_path, key, &bs, &bq, &bms);
+  std::string modes;
+  const bool hit = cache_lookup(cache_path, key, &bs, &bq, &bms, &modes);
   if (!hit) {
-    bms = 1e300;
+    // fewest stream groups within 3% of the fastest form: extra streams are
+    // kept only for a clear gain (their launches then time as overlapping)
+    std::vector<std::array<double, 3>> tried;   // groups, policy, ms
+    double best = 1e300;
     for (int q = 0; q <= (h->gdt >= 2 ? 2 : 1); ++q)
       for (int g : {1, 2, 4, 8}) {
         if (g > h->p) continue;
         if ((rc = ddps_set_execution(h, g, 0, q))) return rc;
         if ((rc = ddps_factor(h))) return rc;       // warm-up
         if ((rc = ddps_factor(h))) return rc;
-        if (h->t_factor_ms < bms) {
-          bms = h->t_factor_ms;
-          bs = g;
-          bq = q;
-        }
+        tried.push_back({(double)g, (double)q, h->t_factor_ms});
+        best = std::min(best, h->t_factor_ms);
+      }
+    bms = 1e300;
+    int bg = 1 << 30;
+    for (auto& c : tried)
+      if (c[2] <= 1.03 * best && ((int)c[0] < bg || ((int)c[0] == bg && c[2] < bms))) {
+        bg = (int)c[0];
+        bs = bg;
+        bq = (int)c[1];
+        bms = c[2];
       }
   }
-  if (!hit || bq == 3) {
+  bool stored = false;
+  if (hit && bq == 3 && !modes.empty()) {
+    // the cached per-launch tiles, if they fit this schedule
+    h->mode_choice.assign(modes.size(), 1);
+    for (size_t i = 0; i < modes.size(); ++i) h->mode_choice[i] = (int8_t)(modes[i] - '0');
+    if ((rc = ddps_set_execution(h, bs, 0, 3))) return rc;
+    stored = h->mode_cursor == (int)modes.size();
+  }
+  if (!hit || (bq == 3 && !stored)) {
     // per-launch tile choice for the chosen group count: every factor GEMM
     // launch is timed under each policy (same launch sequence), and takes
     // the tile of the policy under which it ran fastest
@@ -1949,7 +1998,11 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
       if (!hit) bms = ms3;
     }
   }
-  if (!hit) cache_store(cache_path, key, bs, bq, bms);
+  if (!hit || (bq == 3 && !stored)) {
+    std::string ms_str;
+    for (int8_t v : h->mode_choice) ms_str.push_back((char)('0' + v));
+    cache_store(cache_path, key, bs, bq, bms, ms_str);
+  }
   const int graph = h->use_graph ? 1 : 0;
   if ((rc = ddps_set_execution(h, bs, graph, bq))) return rc;
   if ((rc = ddps_factor(h))) return rc;

@@ -387,7 +387,8 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
       }
 }
 
-// mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only)
+// mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only),
+// 3 = 128 x 128 tiles with 64-deep K chunks (bf16 only; otherwise as 1)
 void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s) {
   if (nwg <= 0 || nprob <= 0) return;
   const dim3 g(nwg), b(256);
@@ -404,6 +405,10 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
   }
   const bool split = dtype == 2;
   switch (mode) {
+    case 3:
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
+      break;
     case 2:
       if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);
       else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);

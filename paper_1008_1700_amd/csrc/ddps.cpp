@@ -45,7 +45,7 @@ struct Launch {
   int nwg;
   double flops;
   double bytes;
-  int mode;  // GEMM tile shape: 0 = 64 x 64, 1 = 128 x 128
+  int mode;  // GEMM: tile mode; GEMV: 1 = every problem 16-byte aligned (wide loads)
 };
 
 struct TimingRec {
@@ -275,11 +275,13 @@ struct ScheduleBuilder {
   int64_t off = 0;
   int nwg = 0;
   double flops = 0, bytes = 0;
+  bool gemv_aligned = true;
 
   void begin(int k) {
     kind = k;
     nwg = 0;
     flops = bytes = 0;
+    gemv_aligned = true;
     off = k == LK_GEMM ? (int64_t)gemm.size() : k == LK_PANEL ? (int64_t)panel.size() : (int64_t)gemv.size();
   }
   // Tile mode the policy asks for (0: 64 x 64, 1: 128 x 128, 2: 256 x 128).
@@ -314,7 +316,7 @@ struct ScheduleBuilder {
   void end(std::vector<Launch>& out) {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
                                                                               : (int64_t)gemv.size()) - off;
-    const int mode = kind == LK_GEMM ? finish_gemm() : 0;
+    const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
     if (cnt > 0 && nwg > 0) {
       out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode});
       if (kind == LK_GEMM) ++h->mode_cursor;
@@ -322,7 +324,7 @@ struct ScheduleBuilder {
   }
   Launch end_one() {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
-    const int mode = kind == LK_GEMM ? finish_gemm() : 0;
+    const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
     return Launch{kind, off, (int)cnt, nwg, flops, bytes, mode};
   }
   void add_gemm(const void* A, int lda, const void* B, int ldb, const void* C0, int ldc0, void* D, int ldd,
@@ -349,6 +351,8 @@ struct ScheduleBuilder {
   void add_gemv(const GemvProb& G0, double elt_bytes) {
     GemvProb G = G0;
     if (G.rows <= 0) return;
+    gemv_aligned = gemv_aligned && reinterpret_cast<uintptr_t>(G.A) % 16 == 0 &&
+                   (G.lda * (int64_t)elt_bytes) % 16 == 0;
     G.wg0 = nwg;
     nwg += G.rows / 64;
     double cols = std::max(0, G.ce - G.cb);
@@ -701,7 +705,9 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
     case LK_TIPMV:
       launch_tipmv(h->sdt, R, h->tip_nseg, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
       break;
-    default: launch_gemv(h->sdt, R, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s); break;
+    default:
+      launch_gemv(h->sdt, R, L.mode == 1, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
+      break;
   }
   h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV || L.kind == LK_TIPMV ? R : 1), L.bytes, s);
   return DDPS_OK;

@@ -137,7 +137,8 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
 void gemm_tile_shape(int dtype, int mode, int* bm, int* bn);
 void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
                   unsigned long long* bad, hipStream_t s);
-void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+// wide: every problem's A and column stride are 16-byte aligned (k_gemv_w)
+void launch_gemv(int dtype, int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
 // reduced-matrix product on the packed tips (same records as launch_gemv,
 // A = first packed row, lda = 2t; nrhs 1 or 2; nseg from tipmv_segments, 0 if

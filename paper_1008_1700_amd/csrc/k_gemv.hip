@@ -113,6 +113,120 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvProb* __restrict__ probs
 }
 
 // ------------------------------------------------------------------------
+// Wide-load form of k_gemv for 16-byte aligned problems: a lane reads VEC
+// consecutive rows of one column in one 16-byte load, so one wave load
+// covers 64 rows of VEC columns (1 KB) instead of 64 rows of one column.
+// The VEC column slots of a wave are summed by lane shuffles, the 4 waves
+// through LDS; epilogue, flags and partial sums as in k_gemv.
+// ------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ probs, int nprob,
+                                                int64_t ldx, int64_t ldy,
+                                                const double* __restrict__ dotv,
+                                                double* __restrict__ partial,
+                                                const int32_t* __restrict__ stop) {
+  constexpr int VEC = 16 / sizeof(T);   // rows per lane
+  constexpr int LPC = 64 / VEC;         // lanes per column
+  constexpr int STEP = 4 * VEC;         // columns per round of the workgroup
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  __shared__ double red[4][64][R];
+  if (stop) {
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < R; ++j) all &= stop[j] != KS_RUNNING;
+    if (all) return;
+  }
+  const int wg = blockIdx.x;
+  const GemvProb& Pg = probs[find_gemv(probs, nprob, wg)];
+  const GemvProb P = Pg;
+  const int r0 = (wg - P.wg0) * 64;
+  int cb = P.cb, ce = P.ce;
+  if (P.tri == 1) ce = min(ce, r0 + 64);
+  if (P.tri == 2) cb = max(cb, r0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane / LPC;             // column slot of this lane
+  const int rl = (lane % LPC) * VEC;    // first local row of this lane
+  const int fl = P.flags;
+  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP;
+  const T* __restrict__ A = (const T*)P.A + r0 + rl;
+  const int64_t lda = P.lda;
+  const int split = P.split;
+
+  double acc[VEC][R];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[e][j] = 0.0;
+
+  auto add = [&](const vec_t& a, int cc) __attribute__((always_inline)) {
+    double xv[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) xv[j] = cc < split ? P.x1[cc + j * ldx] : P.x2[(cc - split) + j * ldx];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int rr = r0 + rl + e;
+      double av = (double)a[e];
+      if (mlu) av = rr > cc ? av : (rr == cc ? 1.0 : 0.0);
+      if (mup) av = rr <= cc ? av : 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) acc[e][j] += av * xv[j];
+    }
+  };
+  int c = cb + g * VEC + q;
+  // four independent columns per lane per step for memory-level parallelism
+  for (; c + 3 * STEP < ce; c += 4 * STEP) {
+    vec_t a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = *(const vec_t*)(A + (int64_t)(c + u * STEP) * lda);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(a[u], c + u * STEP);
+  }
+  for (; c < ce; c += STEP) add(*(const vec_t*)(A + (int64_t)c * lda), c);
+  // sum the column slots of the wave (lanes with equal lane % LPC)
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      for (int off = LPC; off < 64; off <<= 1) acc[e][j] += __shfl_xor(acc[e][j], off, 64);
+  if (lane < LPC) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+      for (int j = 0; j < R; ++j) red[g][rl + e][j] = acc[e][j];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int r = r0 + lane;
+    double dot[R], dd[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      double s = red[0][lane][j] + red[1][lane][j] + red[2][lane][j] + red[3][lane][j];
+      if (fl & V_MASK) s *= P.mask[r];
+      if (fl & V_NEG) s = -s;
+      if (fl & V_YIN) s += P.yin[r + j * ldy];
+      if (r >= P.row_skip) P.yout[r + j * ldy] = s;
+      dot[j] = (fl & V_DOT) ? dotv[P.dot_off + r + j * ldy] * s : 0.0;
+      dd[j] = (fl & V_DOT2) ? s * s : 0.0;
+    }
+    if (fl & V_DOT) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        double v = dot[j], w = dd[j];
+        for (int off = 32; off > 0; off >>= 1) {
+          v += __shfl_xor(v, off, 64);
+          w += __shfl_xor(w, off, 64);
+        }
+        if (lane == 0) {
+          partial[((int64_t)wg * R + j) * 2 + 0] = v;
+          partial[((int64_t)wg * R + j) * 2 + 1] = w;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
 // Reduced-matrix product on packed spike tips.  The rows of G^ are the
 // first and last t rows of each spike G_i (2t columns each), which inside
 // the column-major spikes are 4t-byte column pieces N_i apart.  After every
@@ -283,22 +397,26 @@ void pack_tips(int dtype, int p, int t, const BlockInfo* blocks, const void* spi
 }
 
 template <typename T>
-static void gemv_dispatch(int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+static void gemv_dispatch(int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                           int64_t ldy, const double* dotv, double* partial, const int32_t* stop,
                           hipStream_t s) {
-  switch (nrhs) {
-    case 1: hipLaunchKernelGGL((k_gemv<T, 1>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break;
-    case 2: hipLaunchKernelGGL((k_gemv<T, 2>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break;
-    case 4: hipLaunchKernelGGL((k_gemv<T, 4>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break;
-    default: hipLaunchKernelGGL((k_gemv<T, 8>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break;
+#define DDPS_GEMV(K)                                                                                           \
+  switch (nrhs) {                                                                                              \
+    case 1: hipLaunchKernelGGL((K<T, 1>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break; \
+    case 2: hipLaunchKernelGGL((K<T, 2>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break; \
+    case 4: hipLaunchKernelGGL((K<T, 4>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break; \
+    default: hipLaunchKernelGGL((K<T, 8>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop); break; \
   }
+  if (wide) { DDPS_GEMV(k_gemv_w) }
+  else { DDPS_GEMV(k_gemv) }
+#undef DDPS_GEMV
 }
 
-void launch_gemv(int dtype, int nrhs, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+void launch_gemv(int dtype, int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s) {
   if (nwg <= 0 || nprob <= 0) return;
-  if (dtype == 0) gemv_dispatch<double>(nrhs, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
-  else gemv_dispatch<float>(nrhs, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
+  if (dtype == 0) gemv_dispatch<double>(nrhs, wide, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
+  else gemv_dispatch<float>(nrhs, wide, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
 }
 
 }  // namespace ddps

@@ -217,8 +217,9 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
  * 64 x 64 tiles only, 2 for 256 x 128 tiles where every problem allows them
  * (bf16 arithmetic; otherwise as 0), 3 for a tile chosen per launch by
  * ddps_autotune (as 0 until the autotuner has run), 4 for 128 x 128 tiles
- * with 64-deep K chunks where every problem allows them (bf16 arithmetic;
- * otherwise as 0).  Rebuilds the launch
+ * with 64-deep K chunks and 5 for 256 x 256 tiles on 8 waves, each where
+ * every problem allows them (bf16 arithmetic; otherwise as 0).  Rebuilds the
+ * launch
  * schedules; call before ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM,
  * DDPS_E_HIP. */
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);

@@ -289,6 +289,7 @@ struct ScheduleBuilder {
     if (h->tile_policy == 3)
       return h->mode_cursor < (int)h->mode_choice.size() ? h->mode_choice[h->mode_cursor] : 1;
     if (h->tile_policy == 4) return 3;
+    if (h->tile_policy == 5) return 4;
     return h->tile_policy == 1 ? 0 : (h->tile_policy == 2 && h->gdt >= 2) ? 2 : 1;
   }
   // GEMM launches: the requested tile, narrowed to the largest one every
@@ -300,6 +301,7 @@ struct ScheduleBuilder {
     for (size_t q = (size_t)off; q < gemm.size(); ++q) {
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
       else if (mode == 2 && gemm[q].M < 256) mode = 1;
+      else if (mode == 4 && (gemm[q].M < 256 || gemm[q].N < 256)) mode = 1;
     }
     int BM, BN;
     gemm_tile_shape(h->gdt, mode, &BM, &BN);
@@ -1787,7 +1789,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
 }
 
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
-  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 4) return DDPS_E_ARG;
+  if (!h || streams < 0 || tile_policy < 0 || tile_policy > 5) return DDPS_E_ARG;
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipStreamSynchronize(h->fstream));
   h->groups = streams > 0 ? streams : default_groups(h);
@@ -1845,7 +1847,7 @@ bool cache_lookup(const char* path, const std::string& key, int* streams, int* p
   const std::string tag = "\"modes\": \"";
   const size_t mp = txt.find(tag, br);
   if (mp != std::string::npos && mp < end)
-    for (size_t i = mp + tag.size(); i < txt.size() && txt[i] >= '0' && txt[i] <= '3'; ++i) modes->push_back(txt[i]);
+    for (size_t i = mp + tag.size(); i < txt.size() && txt[i] >= '0' && txt[i] <= '4'; ++i) modes->push_back(txt[i]);
   return true;
 }
 
@@ -1923,10 +1925,10 @@ int time_gemm_launches(ddps_ctx* h, std::vector<float>& out) {
 // each fixed policy, keep per launch the tile of the fastest, and time the
 // resulting schedule (*ms).  Leaves the handle factored with policy 3.
 int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
-  // fixed policies 0, 1, 2 and 4 ask for tile modes 1, 0, 2 and 3
-  static const int8_t mode_of_policy[4] = {1, 0, 2, 3};
-  static const int policy_of[4] = {0, 1, 2, 4};
-  const int nq = h->gdt >= 2 ? 4 : 2;
+  // fixed policies 0, 1, 2, 4 and 5 ask for tile modes 1, 0, 2, 3 and 4
+  static const int8_t mode_of_policy[5] = {1, 0, 2, 3, 4};
+  static const int policy_of[5] = {0, 1, 2, 4, 5};
+  const int nq = h->gdt >= 2 ? 5 : 2;
   std::vector<std::vector<float>> t(nq);
   int rc;
   std::vector<float> t2;

@@ -208,10 +208,12 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
 // ------------------------------------------------------------------------
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <bool SPLIT, int BM, int BN, int OCC = 1, int ST = 1, int BK = 32>
-__global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
+template <bool SPLIT, int BM, int BN, int OCC = 1, int ST = 1, int BK = 32, int NW = 4>
+__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
+  // NW waves in a 2 x NW/2 arrangement, wave tile BM/2 x 2BN/NW of 32 x 32 blocks
+  constexpr int NT = 64 * NW;
   constexpr int LDK = BK + 8;
-  constexpr int MB = BM / 64, NB = BN / 64;     // 32 x 32 blocks per wave (wave tile BM/2 x BN/2)
+  constexpr int MB = BM / 64, NB = BN / (16 * NW);
   constexpr int NS = SPLIT ? 2 : 1;
   __shared__ __attribute__((aligned(16))) __bf16 As[ST][NS][BM][LDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][NS][BN][LDK];
@@ -241,8 +243,8 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
   // B chunk BK x BN: thread -> one column, BKT consecutive k (float4 loads,
   // 16-byte LDS stores).
   constexpr int AROWG = BM / 4;
-  constexpr int AK = BK * AROWG / 256;
-  constexpr int BKT = BK * BN / 256;
+  constexpr int AK = BK * AROWG / NT;
+  constexpr int BKT = BK * BN / NT;
   static_assert(AK >= 1 && BKT % 8 == 0, "chunk split");
   const int arg = tid % AROWG, akg = tid / AROWG;
   const int ar = I0 + 4 * arg;
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
       bf16x8 xh[NB], xl[NB], yh[MB], yl[MB];
 #pragma unroll
       for (int ni = 0; ni < NB; ++ni) {
-        const int n = wn * (BN / 2) + ni * 32 + (lane & 31);
+        const int n = wn * (2 * BN / NW) + ni * 32 + (lane & 31);
         xh[ni] = *(const bf16x8*)&Bs[st][0][n][kk];
         if (SPLIT) xl[ni] = *(const bf16x8*)&Bs[st][NS - 1][n][kk];
       }
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = I0 + wm * (BM / 2) + mi * 32 + (lane & 31);
-        const int c = J0 + wn * (BN / 2) + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int c = J0 + wn * (2 * BN / NW) + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         if (r < P.M && c < P.N) {
           float val = acc[mi][ni][v];
           if (neg) val = -val;
@@ -388,7 +390,8 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16(const GemmProb* __restri
 }
 
 // mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only),
-// 3 = 128 x 128 tiles with 64-deep K chunks (bf16 only; otherwise as 1)
+// 3 = 128 x 128 tiles with 64-deep K chunks (bf16 only; otherwise as 1),
+// 4 = 256 x 256 tiles on 8 waves (bf16 only; otherwise as 1)
 void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s) {
   if (nwg <= 0 || nprob <= 0) return;
   const dim3 g(nwg), b(256);
@@ -405,6 +408,10 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
   }
   const bool split = dtype == 2;
   switch (mode) {
+    case 4:
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 256, 1, 1, 32, 8>), g, dim3(512), 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 256, 1, 1, 32, 8>), g, dim3(512), 0, s, probs, nprob);
+      break;
     case 3:
       if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
       else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
@@ -426,7 +433,8 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
 
 // tile edge (rows, columns) of a launch mode
 void gemm_tile_shape(int dtype, int mode, int* bm, int* bn) {
-  if (mode == 2 && dtype >= 2) { *bm = 256; *bn = 128; }
+  if (mode == 4 && dtype >= 2) { *bm = 256; *bn = 256; }
+  else if (mode == 2 && dtype >= 2) { *bm = 256; *bn = 128; }
   else if (mode >= 1) { *bm = 128; *bn = 128; }
   else { *bm = 64; *bn = 64; }
 }

@@ -108,13 +108,14 @@ def test_autotune_and_cache(tmp_path):
 
 def test_bf16x3_tile_policies_agree():
     """The 256 x 128 bf16 tile (policy 2), the 128 x 128 tile (policy 0, and
-    policy 4 with 64-deep K chunks) and the 64 x 64 tile (policy 1) compute
+    policy 4 with 64-deep K chunks), the 256 x 256 tile on 8 waves (policy 5)
+    and the 64 x 64 tile (policy 1) compute
     the same split-bf16 products; tiles
     with t = 256 let policy 2 take the large tile on most launches."""
     from paper_1008_1700_amd import ddps
     d = configs.small_banded(4, [700, 900, 600, 820], 200, 23)
     xs = {}
-    for policy in (0, 2, 1, 4):
+    for policy in (0, 2, 1, 4, 5):
         S = make_solver(d, dtype="bf16x3", inner_tol=1e-8)
         try:
             ddps.ddps_set_execution(S.h, 1, False, policy)
@@ -135,4 +136,4 @@ def test_bf16x3_tile_policies_agree():
     finally:
         S.close()
     assert relerr(xs[2], d["x_star"]) <= 1e-9
-    assert all(relerr(xs[q], xs[0]) <= 1e-10 for q in (1, 2, 3, 4))
+    assert all(relerr(xs[q], xs[0]) <= 1e-10 for q in (1, 2, 3, 4, 5))

@@ -222,6 +222,34 @@ def test_ragged_systems(sizes, b, seed):
         S.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ragged_many_rhs_unaligned_products(dtype):
+    """Four right-hand sides on blocks whose padding is not a multiple of
+    16 bytes: the reduced products then run on the column-major spikes at
+    unaligned row offsets (the one-column-per-load GEMV), and every column
+    must match the oracle's direct solution."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    d = configs.small_banded(3, [150, 201, 170], 5, 2)    # t = 64, pads 42 / 55 / 22
+    A = d["A"]
+    rng = np.random.default_rng(11)
+    Xs = rng.uniform(-1, 1, (4, A.n))
+    F = np.stack([A.scipy() @ x for x in Xs])
+    S = make_solver(d, dtype=dtype, inner_tol=1e-14 if dtype == "f64" else 1e-8, max_rhs=4)
+    try:
+        S.factor()
+        Fd = dev_vec(F)
+        Xd = torch.zeros_like(Fd)
+        rc, info = ddps.ddps_solve_many(S.h, Fd, Xd, 1e-12)
+        assert info.relres_inf <= 1e-12
+        for j in range(4):
+            xo, _, _ = O.solve(A.n, A.row_ptr, A.col, A.val, d["part_ptr"], F[j], outer="none")
+            assert relerr(host(Xd)[j], xo) <= 1e-9
+    finally:
+        S.close()
+
+
 def test_ragged_spikes_and_padding():
     from paper_1008_1700_amd import ddps
     torch = torch_cuda()

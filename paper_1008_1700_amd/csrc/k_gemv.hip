@@ -234,8 +234,10 @@ __global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ pro
 // streams each row as one contiguous run: a wave owns a row at a time, its
 // lanes read consecutive 16-byte pieces of it, the right-hand-side entries
 // come from L1/L2 (2t values shared by every row of the part), and the row
-// sum is a wave reduction.  Same problem records, flags and partial-sum
-// layout as k_gemv (A = first packed row, lda = row length 2t).
+// sum is a wave reduction.  Lane rr keeps the sum of the wave's row rr,
+// and one epilogue per wave then serves its 16 rows at once.  Same problem
+// records, flags and partial-sum layout as k_gemv (A = first packed row,
+// lda = row length 2t).
 // ------------------------------------------------------------------------
 template <typename T, int R, int NSEG>
 __global__ __launch_bounds__(256) void k_tipmv(const GemvProb* __restrict__ probs, int nprob,
@@ -273,9 +275,11 @@ __global__ __launch_bounds__(256) void k_tipmv(const GemvProb* __restrict__ prob
         xr[sg][e][j] = v;
       }
     }
-  double dot[R], dd[R];
+  // row rr's sum is kept by lane rr; one epilogue per wave for its 16 rows
+  double mine[R];
 #pragma unroll
-  for (int j = 0; j < R; ++j) dot[j] = dd[j] = 0.0;
+  for (int j = 0; j < R; ++j) mine[j] = 0.0;
+#pragma unroll 2
   for (int rr = 0; rr < RPW; ++rr) {
     const int r = rbase + rr;
     const T* __restrict__ Arow = (const T*)P.A + (int64_t)r * P.lda + cb;
@@ -296,22 +300,34 @@ __global__ __launch_bounds__(256) void k_tipmv(const GemvProb* __restrict__ prob
 #pragma unroll
         for (int j = 0; j < R; ++j) acc[j] += (double)a[sg][e] * xr[sg][e][j];
 #pragma unroll
-    for (int j = 0; j < R; ++j)
+    for (int j = 0; j < R; ++j) {
       for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
-    if (lane == 0) {
+      mine[j] = lane == rr ? acc[j] : mine[j];
+    }
+  }
+  double dot[R], dd[R];
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        double v = acc[j];
-        if (fl & V_MASK) v *= P.mask[r];
-        if (fl & V_NEG) v = -v;
-        if (fl & V_YIN) v += P.yin[r + j * ldy];
-        P.yout[r + j * ldy] = v;
-        if (fl & V_DOT) dot[j] += dotv[P.dot_off + r + j * ldy] * v;
-        if (fl & V_DOT2) dd[j] += v * v;
-      }
+  for (int j = 0; j < R; ++j) dot[j] = dd[j] = 0.0;
+  if (lane < RPW) {
+    const int r = rbase + lane;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      double v = mine[j];
+      if (fl & V_MASK) v *= P.mask[r];
+      if (fl & V_NEG) v = -v;
+      if (fl & V_YIN) v += P.yin[r + j * ldy];
+      P.yout[r + j * ldy] = v;
+      if (fl & V_DOT) dot[j] = dotv[P.dot_off + r + j * ldy] * v;
+      if (fl & V_DOT2) dd[j] = v * v;
     }
   }
   if (fl & (V_DOT | V_DOT2)) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      for (int off = RPW / 2; off > 0; off >>= 1) {
+        dot[j] += __shfl_xor(dot[j], off, 64);
+        dd[j] += __shfl_xor(dd[j], off, 64);
+      }
     if (lane == 0)
 #pragma unroll
       for (int j = 0; j < R; ++j) {

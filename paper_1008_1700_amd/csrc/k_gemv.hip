@@ -173,16 +173,56 @@ __global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ pro
       for (int j = 0; j < R; ++j) acc[e][j] += av * xv[j];
     }
   };
-  int c = cb + g * VEC + q;
-  // four independent columns per lane per step for memory-level parallelism
-  for (; c + 3 * STEP < ce; c += 4 * STEP) {
-    vec_t a[4];
+  if constexpr (R >= 4) {
+    // many right-hand sides: the vector entries of each round of 4 STEP
+    // columns are staged once per workgroup in LDS (double-buffered), so a
+    // lane reads its columns' R entries as 16-byte LDS reads instead of R
+    // separate global loads
+    constexpr int RC = 4 * STEP;   // columns per round
+    __shared__ __attribute__((aligned(16))) double xs[2][RC][R];
+    int buf = 0;
+    for (int c0 = cb; c0 < ce; c0 += RC) {
+      for (int i = tid; i < RC * R; i += 256) {
+        const int cc = c0 + i / R, j = i % R;
+        xs[buf][i / R][j] = cc < ce ? (cc < split ? P.x1[cc + j * ldx] : P.x2[(cc - split) + j * ldx]) : 0.0;
+      }
+      __syncthreads();
+      vec_t a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = *(const vec_t*)(A + (int64_t)(c + u * STEP) * lda);
+      for (int u = 0; u < 4; ++u) {
+        const int cc = c0 + g * VEC + q + u * STEP;
+        a[u] = cc < ce ? *(const vec_t*)(A + (int64_t)cc * lda) : vec_t{};
+      }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) add(a[u], c + u * STEP);
+      for (int u = 0; u < 4; ++u) {
+        const int cl = g * VEC + q + u * STEP, cc = c0 + cl;
+        double xv[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) xv[j] = xs[buf][cl][j];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const int rr = r0 + rl + e;
+          double av = (double)a[u][e];
+          if (mlu) av = rr > cc ? av : (rr == cc ? 1.0 : 0.0);
+          if (mup) av = rr <= cc ? av : 0.0;
+#pragma unroll
+          for (int j = 0; j < R; ++j) acc[e][j] += av * xv[j];
+        }
+      }
+      buf ^= 1;
+    }
+  } else {
+    int c = cb + g * VEC + q;
+    // four independent columns per lane per step for memory-level parallelism
+    for (; c + 3 * STEP < ce; c += 4 * STEP) {
+      vec_t a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = *(const vec_t*)(A + (int64_t)(c + u * STEP) * lda);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add(a[u], c + u * STEP);
+    }
+    for (; c < ce; c += STEP) add(*(const vec_t*)(A + (int64_t)c * lda), c);
   }
-  for (; c < ce; c += STEP) add(*(const vec_t*)(A + (int64_t)c * lda), c);
   // sum the column slots of the wave (lanes with equal lane % LPC)
 #pragma unroll
   for (int e = 0; e < VEC; ++e)

@@ -767,8 +767,9 @@ int enqueue_factor(ddps_ctx* h) {
   const int G = (int)h->sch_group.size();
   // with per-launch timing of the factor kernels the groups run one after
   // another on the factor stream, so that each launch's event interval holds
-  // its own kernel only (same launches, no overlap between groups)
-  const bool serial = h->tim_on[TK_GEMM] || h->tim_on[TK_PANEL];
+  // its own kernel only (same launches, no overlap between groups); a graph
+  // being captured carries no events and keeps the concurrent form
+  const bool serial = (h->tim_on[TK_GEMM] || h->tim_on[TK_PANEL]) && !h->capturing;
   if (G <= 1 || serial) {
     for (int g = 0; g < G; ++g)
       if ((rc = run_schedule(h, h->sch_group[g], 1, 0, 0, TK_GEMM, f))) return rc;

@@ -212,31 +212,31 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
 /* Execution form of ddps_factor (the method's result does not depend on it):
  * streams = stream groups over which the blocks are distributed (blocks of
  * different groups factor concurrently; 0 = automatic), graph = 1 to capture
- * the factorisation once as a HIP graph and replay it, tile_policy = 0 for
- * 128 x 128 GEMM tiles where every problem of a launch allows them, 1 for
- * 64 x 64 tiles only, 2 for 256 x 128 tiles where every problem allows them
- * (bf16 arithmetic; otherwise as 0), 3 for a tile chosen per launch by
- * ddps_autotune (as 0 until the autotuner has run), 4 for 128 x 128 tiles
- * with 64-deep K chunks and 5 for 256 x 256 tiles on 8 waves, each where
- * every problem allows them (bf16 arithmetic; otherwise as 0).  Rebuilds the
- * launch
- * schedules; call before ddps_factor.  Errors: DDPS_E_ARG, DDPS_E_NOMEM,
- * DDPS_E_HIP. */
+ * the factorisation once as a HIP graph and replay it, and tile_policy the
+ * GEMM tile of each launch:
+ *   0  128 x 128 where every problem of the launch allows it,
+ *   1  64 x 64 only,
+ *   2  256 x 128 where every problem allows it (bf16 arithmetic, else as 0),
+ *   3  a tile chosen per launch by ddps_autotune (as 0 until it has run),
+ *   4  128 x 128 with 64-deep K chunks (bf16 arithmetic, else as 0),
+ *   5  256 x 256 on 8 waves (bf16 arithmetic, else as 0).
+ * Rebuilds the launch schedules; call before ddps_factor.  Errors:
+ * DDPS_E_ARG, DDPS_E_NOMEM, DDPS_E_HIP. */
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
-/* Autotuner of the execution form: times ddps_factor on the device for
- * stream groups {1, 2, 4, 8} (at most p) and every tile policy (2 only for
- * the bf16 dtypes) and takes the fewest groups within 3% of the fastest form;
- * then, for that group count, times every GEMM launch
- * of the factorisation under each policy and builds policy 3 from the
- * fastest tile of each launch.  It keeps the fastest form, and records it
- * (policy 3 is re-derived on a cache hit) in the JSON file cache_path (may be
- * NULL) under a
- * key made of the GPU architecture, factor dtype, tile size t, p and the
- * largest tile-row count; a later call with the same key takes the cached
- * choice without timing.  Host outputs (may be NULL): chosen streams, tile
- * policy and its factor time in milliseconds.  The handle is left factored
- * with the chosen form. */
+/* Autotuner of the execution form.  It times ddps_factor on the device for
+ * stream groups {1, 2, 4, 8} (at most p) and tile policies 0, 1 and 2 (2
+ * only for the bf16 dtypes), and takes the fewest groups within 3% of the
+ * fastest form.  For that group count it then times every GEMM launch of the
+ * factorisation under each fixed policy (0, 1, 2, 4, 5 for the bf16 dtypes;
+ * 0, 1 otherwise) and builds policy 3 from the fastest tile of each launch,
+ * kept if the whole factorisation is faster.  The choice, with policy 3's
+ * per-launch tiles, is recorded in the JSON file cache_path (may be NULL)
+ * under a key made of the GPU architecture, factor dtype, tile size t, p and
+ * the largest tile-row count; a later call with the same key takes the
+ * cached choice without timing.  Host outputs (may be NULL): chosen streams,
+ * tile policy and its factor time in milliseconds.  The handle is left
+ * factored with the chosen form. */
 int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy,
                   double* factor_ms);
 

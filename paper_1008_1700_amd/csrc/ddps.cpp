@@ -301,7 +301,7 @@ struct ScheduleBuilder {
     for (size_t q = (size_t)off; q < gemm.size(); ++q) {
       if (gemm[q].M < 128 || gemm[q].N < 128) mode = 0;
       else if (mode == 2 && gemm[q].M < 256) mode = 1;
-      else if (mode == 4 && (gemm[q].M < 256 || gemm[q].N < 256)) mode = 1;
+      else if (mode == 4 && (gemm[q].M < 256 || gemm[q].N < 256)) mode = 3;
     }
     int BM, BN;
     gemm_tile_shape(h->gdt, mode, &BM, &BN);

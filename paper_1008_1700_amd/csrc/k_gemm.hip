@@ -24,6 +24,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+// The problem records hold generic pointers; loads through them compile to
+// flat loads, which also count against the LDS wait counter, so every wait
+// for LDS would wait for them too.  Casting to the global address space gives
+// global loads and stores with their own counter.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> using gmut = __attribute__((address_space(1))) T*;
+__device__ __forceinline__ float4 gload4(const float* p) {
+  const f32x4 v = *(gptr<f32x4>)p;
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // Logical workgroup index such that each XCD (hardware dispatches workgroups
 // round-robin over the 8 XCDs) receives one contiguous range of tiles: tiles
 // of the same block then share that XCD's L2.
@@ -109,8 +120,8 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
   const int fl = P.flags;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const T* __restrict__ A = (const T*)P.A;
-  const T* __restrict__ B = (const T*)P.B;
+  gptr<T> A = (gptr<T>)P.A;
+  gptr<T> B = (gptr<T>)P.B;
   const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
 
   acc_t acc[MB][NB];
@@ -134,7 +145,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
       const int c = k0 + ak + ASTEP * i;
       ra[i] = select_op(A[(int64_t)c * P.lda + arow], I0 + am, c, a_lu, a_up, P.M, 1 << 30);
     }
-    const T* bp = B + (int64_t)bcol * P.ldb + k0 + bk0;
+    gptr<T> bp = B + (int64_t)bcol * P.ldb + k0 + bk0;
 #pragma unroll
     for (int i = 0; i < BE; ++i) rb[i] = select_op(bp[i], k0 + bk0 + i, J0 + bn, b_lu, b_up, 1 << 30, P.N);
   };
@@ -172,10 +183,32 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
     }
   }
 
-  // Epilogue: lane holds D[row = .. + (lane&15)][col = .. + Mma::row(lane, v)]
-  const T* __restrict__ C0 = (const T*)P.C0;
-  T* __restrict__ D = (T*)P.D;
-  const bool has_c0 = fl & G_C0, neg = fl & G_NEG;
+  // Epilogue: lane holds D[row = .. + (lane&15)][col = .. + Mma::row(lane, v)].
+  // Whole tiles load their C0 values in one batch per 16 x 16 block.
+  gptr<T> C0 = (gptr<T>)P.C0;
+  gmut<T> D = (gmut<T>)P.D;
+  const bool has_c0 = fl & G_C0;
+  const T sg = (fl & G_NEG) ? T(-1) : T(1);
+  if (I0 + BM <= P.M && J0 + BN <= P.N) {
+#pragma unroll
+    for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NB; ++ni) {
+        const int r = I0 + wm * (BM / 2) + mi * 16 + (lane & 15);
+        const int c = J0 + wn * (BN / 2) + ni * 16;
+        if (has_c0) {
+          T cv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cv[v] = C0[(int64_t)(c + Mma<T>::row(lane, v)) * P.ldc0 + r];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) D[(int64_t)(c + Mma<T>::row(lane, v)) * P.ldd + r] = sg * acc[mi][ni][v] + cv[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) D[(int64_t)(c + Mma<T>::row(lane, v)) * P.ldd + r] = sg * acc[mi][ni][v];
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
@@ -185,8 +218,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
         const int r = I0 + wm * (BM / 2) + mi * 16 + (lane & 15);
         const int c = J0 + wn * (BN / 2) + ni * 16 + Mma<T>::row(lane, v);
         if (r < P.M && c < P.N) {
-          T val = acc[mi][ni][v];
-          if (neg) val = -val;
+          T val = sg * acc[mi][ni][v];
           if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
           D[(int64_t)c * P.ldd + r] = val;
         }
@@ -207,6 +239,52 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
 // (8(v/4) + 4(l/32) + v%4, l%32).
 // ------------------------------------------------------------------------
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Epilogue of MB x NB accumulator blocks of 32 x 32: register v of lane l in
+// block (mi, ni) is D(r0 + 32 mi + l % 32, c0 + 32 ni + 8 (v / 4) + 4 (l / 32) + v % 4),
+// and D = C0 -/+ acc.  Whole tiles (full) load C0 in batches of 16.
+template <int MB, int NB>
+__device__ __forceinline__ void store_tile32(const GemmProb& P, const f32x16 (&acc)[MB][NB], int r0, int c0,
+                                             int lane, bool full) {
+  gptr<float> C0 = (gptr<float>)P.C0;
+  gmut<float> D = (gmut<float>)P.D;
+  const bool has_c0 = P.flags & G_C0;
+  const float sg = (P.flags & G_NEG) ? -1.f : 1.f;
+  if (full) {
+#pragma unroll
+    for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NB; ++ni) {
+        const int r = r0 + mi * 32 + (lane & 31);
+        const int c = c0 + ni * 32 + 4 * (lane >> 5);
+        if (has_c0) {
+          float cv[16];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) cv[v] = C0[(int64_t)(c + 8 * (v >> 2) + (v & 3)) * P.ldc0 + r];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) D[(int64_t)(c + 8 * (v >> 2) + (v & 3)) * P.ldd + r] = sg * acc[mi][ni][v] + cv[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) D[(int64_t)(c + 8 * (v >> 2) + (v & 3)) * P.ldd + r] = sg * acc[mi][ni][v];
+        }
+      }
+    return;
+  }
+#pragma unroll
+  for (int mi = 0; mi < MB; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NB; ++ni)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = r0 + mi * 32 + (lane & 31);
+        const int c = c0 + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (r < P.M && c < P.N) {
+          float val = sg * acc[mi][ni][v];
+          if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
+          D[(int64_t)c * P.ldd + r] = val;
+        }
+      }
+}
 
 template <bool SPLIT, int BM, int BN, int OCC = 1, int ST = 1, int BK = 32, int NW = 4>
 __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
@@ -257,10 +335,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
   auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < AK; ++i)
-      ra[i] = *(const float4*)(A + (int64_t)(k0 + akg * AK + i) * P.lda + arow_ld);
+      ra[i] = gload4(A + (int64_t)(k0 + akg * AK + i) * P.lda + arow_ld);
     const float* bp = B + (int64_t)bcol_ld * P.ldb + k0 + bkg * BKT;
 #pragma unroll
-    for (int i = 0; i < BKT / 4; ++i) rb[i] = *(const float4*)(bp + 4 * i);
+    for (int i = 0; i < BKT / 4; ++i) rb[i] = gload4(bp + 4 * i);
   };
   typedef __bf16 bfa __attribute__((ext_vector_type(AK)));
   // Stage one chunk into LDS as bf16 (hi, and lo = x - hi when split).  The
@@ -368,30 +446,220 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
     }
   }
 
-  // Epilogue: lane holds D[row = .. + (lane&31)][col = .. + 8(v/4) + 4(lane/32) + v%4]
-  const float* __restrict__ C0 = (const float*)P.C0;
-  float* __restrict__ D = (float*)P.D;
-  const bool has_c0 = fl & G_C0, neg = fl & G_NEG;
+  store_tile32<MB, NB>(P, acc, I0 + wm * (BM / 2), J0 + wn * (2 * BN / NW), lane, !a_edge && !b_edge);
+}
+
+
+// ------------------------------------------------------------------------
+// bf16 MFMA with the operands copied from global memory straight into LDS
+// (global_load_lds_dwordx4: each lane's 16 bytes land at lane * 16 of the
+// wave's 1 KiB destination), FP32 in LDS, split into hi/lo in registers as
+// the fragments are read.  No VGPRs hold operands in flight and no staging
+// pass stands between the loads and the products.
+//
+// LDS, two stages of a 32-deep K chunk:
+//   A as [k][m] (m contiguous, as in global memory): one wave instruction
+//     fills 256 / BM rows of k; a fragment (8 consecutive k of one row) is
+//     eight 4-byte reads.
+//   B as [n][k] (k contiguous): one wave instruction fills 8 columns; the
+//     eight 16-byte slots of column n hold k pieces slot ^ (n & 7), so that
+//     the 16-byte fragment reads of 8 consecutive columns hit distinct banks.
+// Per chunk: one barrier (the chunk has landed, the other stage is free), the
+// first 16-deep step's LDS reads, the DMA of the next chunk into the other
+// stage, then the products.  Chunks crossing a packed triangle's diagonal get
+// their masks applied in LDS first (one more barrier).  Rows beyond M and
+// column groups beyond N load clamped in-range data: they only feed outputs
+// that are not stored.  Same split and the same MFMA order per 16-deep step
+// as k_gemm_bf16, so the results are bitwise the same.
+// ------------------------------------------------------------------------
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) void* dma_src_t;
+typedef __attribute__((address_space(3))) void* dma_dst_t;
+
+// hi = bf16(x), lo = bf16(x - hi) for 8 values, converted two at a time
+template <bool SPLIT>
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& h, bf16x8& l) {
 #pragma unroll
-  for (int mi = 0; mi < MB; ++mi)
+  for (int e = 0; e < 8; e += 2) {
+    const f32x2 v = {x[e], x[e + 1]};
+    const bf16x2 hv = __builtin_convertvector(v, bf16x2);
+    h[e] = hv[0];
+    h[e + 1] = hv[1];
+    if (SPLIT) {
+      const f32x2 r = {x[e] - (float)hv[0], x[e + 1] - (float)hv[1]};
+      const bf16x2 lv = __builtin_convertvector(r, bf16x2);
+      l[e] = lv[0];
+      l[e + 1] = lv[1];
+    }
+  }
+}
+
+// One K chunk of k_gemm_dl.  The LDS pointers are restrict: the compiler then
+// sees that the reads of the current stage (ca, cb) do not alias the DMA into
+// the next stage (na, nb), and does not make them wait for it.
+template <bool SPLIT, int BM, int BN, int NW>
+__device__ __forceinline__ void dl_chunk(const float* __restrict__ ca, const float* __restrict__ cb,
+                                         float* __restrict__ na, float* __restrict__ nb,
+                                         const char* __restrict__ ga, const char* __restrict__ gb,
+                                         const int64_t (&goff)[16], bool issue_next, int lane, int wm, int wn,
+                                         f32x16 (&acc)[BM / 64][BN / (16 * NW)]) {
+  constexpr int BK = 32;
+  constexpr int MB = BM / 64, NB = BN / (16 * NW);
+  constexpr int NA = BK * BM / 256 / NW, NBI = BN / 8 / NW;
+  auto read = [&](int ks, float (&xb)[NB][8], float (&xa)[MB][8]) __attribute__((always_inline)) {
+    const int kk = ks * 16 + 8 * (lane >> 5);
 #pragma unroll
-    for (int ni = 0; ni < NB; ++ni)
+    for (int ni = 0; ni < NB; ++ni) {
+      const int n = wn * (2 * BN / NW) + ni * 32 + (lane & 31);
+      const int s0 = (kk >> 2) ^ (n & 7), s1 = ((kk >> 2) + 1) ^ (n & 7);
+      const f32x4 v0 = *(const f32x4*)&cb[n * BK + 4 * s0];
+      const f32x4 v1 = *(const f32x4*)&cb[n * BK + 4 * s1];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = I0 + wm * (BM / 2) + mi * 32 + (lane & 31);
-        const int c = J0 + wn * (2 * BN / NW) + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        if (r < P.M && c < P.N) {
-          float val = acc[mi][ni][v];
-          if (neg) val = -val;
-          if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
-          D[(int64_t)c * P.ldd + r] = val;
-        }
+      for (int e = 0; e < 4; ++e) {
+        xb[ni][e] = v0[e];
+        xb[ni][e + 4] = v1[e];
       }
+    }
+#pragma unroll
+    for (int mi = 0; mi < MB; ++mi) {
+      const int m = wm * (BM / 2) + mi * 32 + (lane & 31);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xa[mi][e] = ca[(kk + e) * BM + m];
+    }
+  };
+  auto mult = [&](const float (&xb)[NB][8], const float (&xa)[MB][8]) __attribute__((always_inline)) {
+    bf16x8 xh[NB], xl[NB];
+#pragma unroll
+    for (int ni = 0; ni < NB; ++ni) split8<SPLIT>(xb[ni], xh[ni], xl[ni]);
+#pragma unroll
+    for (int mi = 0; mi < MB; ++mi) {
+      bf16x8 yh, yl;
+      split8<SPLIT>(xa[mi], yh, yl);
+      if (SPLIT) {
+#pragma unroll
+        for (int ni = 0; ni < NB; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ni], yh, acc[mi][ni], 0, 0, 0);
+#pragma unroll
+        for (int ni = 0; ni < NB; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yl, acc[mi][ni], 0, 0, 0);
+      }
+#pragma unroll
+      for (int ni = 0; ni < NB; ++ni)
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ni], yh, acc[mi][ni], 0, 0, 0);
+    }
+  };
+  float xb[NB][8], xa[MB][8];
+  read(0, xb, xa);
+  __builtin_amdgcn_sched_barrier(0);
+  if (issue_next) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+      __builtin_amdgcn_global_load_lds((dma_src_t)(ga + goff[q]), (dma_dst_t)(na + q * 256), 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < NBI; ++q)
+      __builtin_amdgcn_global_load_lds((dma_src_t)(gb + goff[NA + q]), (dma_dst_t)(nb + q * 256), 16, 0, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  mult(xb, xa);
+#pragma unroll
+  for (int ks = 1; ks < BK / 16; ++ks) {
+    __builtin_amdgcn_sched_barrier(0);
+    read(ks, xb, xa);
+    mult(xb, xa);
+  }
+}
+
+template <bool SPLIT, int BM, int BN, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __restrict__ probs, int nprob) {
+  constexpr int BK = 32;
+  constexpr int MB = BM / 64, NB = BN / (16 * NW);
+  constexpr int NA = BK * BM / 256 / NW;   // A instructions per wave and chunk
+  constexpr int NBI = BN / 8 / NW;         // B instructions per wave and chunk
+  constexpr int KPI = BM >= 256 ? 1 : 256 / BM;   // k rows per A instruction
+  static_assert(BM <= 256 && NA >= 1 && NBI >= 1 && NA + NBI <= 16 && (BK * BM) % (256 * NW) == 0 &&
+                    BN % (8 * NW) == 0 && NB >= 1,
+                "chunk split");
+  __shared__ __attribute__((aligned(16))) float As[2][BK * BM];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * BK];
+
+  const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const GemmProb P = probs[find_prob(probs, nprob, wg)];
+  const TileCoord tc = tile_of<BM, BN>(P, wg);
+  const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
+  const int fl = P.flags;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const char* A = (const char*)P.A;
+  const char* B = (const char*)P.B;
+  const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+
+  f32x16 acc[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  // byte offsets of this lane's 16-byte pieces: a wave-uniform part per
+  // instruction and one per-lane part for A and one for B
+  const int64_t a_lane =
+      ((int64_t)((lane * 4) / BM) * P.lda + min(I0 + (lane * 4) % BM, P.M - 4)) * 4;
+  const int64_t b_lane = ((int64_t)(lane >> 3) * P.ldb + 4 * ((lane & 7) ^ ((lane >> 3) & 7))) * 4;
+  auto a_off = [&](int k, int q) __attribute__((always_inline)) {
+    return (int64_t)(k + (wave * NA + q) * KPI) * P.lda * 4 + a_lane;
+  };
+  auto b_off = [&](int k, int q) __attribute__((always_inline)) {
+    return ((int64_t)min(J0 + 8 * (wave * NBI + q), P.N - 8) * P.ldb + k) * 4 + b_lane;
+  };
+
+  if (kb < ke) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+      __builtin_amdgcn_global_load_lds((dma_src_t)(A + a_off(kb, q)), (dma_dst_t)&As[0][(wave * NA + q) * 256], 16,
+                                       0, 0);
+#pragma unroll
+    for (int q = 0; q < NBI; ++q)
+      __builtin_amdgcn_global_load_lds((dma_src_t)(B + b_off(kb, q)), (dma_dst_t)&Bs[0][(wave * NBI + q) * 256], 16,
+                                       0, 0);
+    int st = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      __syncthreads();   // chunk k0 has landed; every wave is done with the other stage
+      const bool am = (a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM;
+      const bool bm = (b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN;
+      if (am || bm) {
+        if (am)
+          for (int i = tid; i < BK * BM; i += 64 * NW) {
+            const int k = i / BM, m = i % BM;
+            As[st][i] = select_op(As[st][i], I0 + m, k0 + k, a_lu, a_up, 1 << 30, 1 << 30);
+          }
+        if (bm)
+          for (int i = tid; i < BN * BK; i += 64 * NW) {
+            const int n = i / BK, k = 4 * (((i % BK) >> 2) ^ (n & 7)) + (i & 3);
+            Bs[st][i] = select_op(Bs[st][i], k0 + k, J0 + n, b_lu, b_up, 1 << 30, 1 << 30);
+          }
+        __syncthreads();
+      }
+      const int k1 = k0 + BK;
+      int64_t goff[16];
+#pragma unroll
+      for (int q = 0; q < NA; ++q) goff[q] = a_off(k1, q);
+#pragma unroll
+      for (int q = 0; q < NBI; ++q) goff[NA + q] = b_off(k1, q);
+      dl_chunk<SPLIT, BM, BN, NW>(As[st], Bs[st], &As[st ^ 1][wave * NA * 256], &Bs[st ^ 1][wave * NBI * 256], A, B,
+                                  goff, k1 < ke, lane, wm, wn, acc);
+      st ^= 1;
+    }
+  }
+  store_tile32<MB, NB>(P, acc, I0 + wm * (BM / 2), J0 + wn * (2 * BN / NW), lane,
+                       I0 + BM <= P.M && J0 + BN <= P.N);
 }
 
 // mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only),
-// 3 = 128 x 128 tiles with 64-deep K chunks (bf16 only; otherwise as 1),
-// 4 = 256 x 256 tiles on 8 waves (bf16 only; otherwise as 1)
+// 3 = 128 x 128 tiles with direct LDS loads (bf16 only; otherwise as 1),
+// 4 = 256 x 256 tiles on 8 waves with direct LDS loads (bf16 only; otherwise as 1)
 void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s) {
   if (nwg <= 0 || nprob <= 0) return;
   const dim3 g(nwg), b(256);
@@ -409,12 +677,12 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
   const bool split = dtype == 2;
   switch (mode) {
     case 4:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 256, 1, 1, 32, 8>), g, dim3(512), 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 256, 1, 1, 32, 8>), g, dim3(512), 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_dl<false, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob);
       break;
     case 3:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2, 1, 64>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 128, 128, 4, 2>), g, b, 0, s, probs, nprob);
+      else hipLaunchKernelGGL((k_gemm_dl<false, 128, 128, 4, 2>), g, b, 0, s, probs, nprob);
       break;
     case 2:
       if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);

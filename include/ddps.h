@@ -218,19 +218,22 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
  *   1  64 x 64 only,
  *   2  256 x 128 where every problem allows it (bf16 arithmetic, else as 0),
  *   3  a tile chosen per launch by ddps_autotune (as 0 until it has run),
- *   4  128 x 128 with 64-deep K chunks (bf16 arithmetic, else as 0),
- *   5  256 x 256 on 8 waves (bf16 arithmetic, else as 0).
+ *   4  128 x 128 with operands loaded straight into LDS (bf16 arithmetic,
+ *      else as 0),
+ *   5  256 x 256 on 8 waves, operands loaded straight into LDS (bf16
+ *      arithmetic, else as 0; launches with a side below 256 take 4's tile).
  * Rebuilds the launch schedules; call before ddps_factor.  Errors:
  * DDPS_E_ARG, DDPS_E_NOMEM, DDPS_E_HIP. */
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
 /* Autotuner of the execution form.  It times ddps_factor on the device for
- * stream groups {1, 2, 4, 8} (at most p) and tile policies 0, 1 and 2 (2
- * only for the bf16 dtypes), and takes the fewest groups within 3% of the
- * fastest form.  For that group count it then times every GEMM launch of the
- * factorisation under each fixed policy (0, 1, 2, 4, 5 for the bf16 dtypes;
- * 0, 1 otherwise) and builds policy 3 from the fastest tile of each launch,
- * kept if the whole factorisation is faster.  The choice, with policy 3's
+ * stream groups {1, 2, 4, 8} (at most p) and the fixed tile policies (0, 1,
+ * 2, 4, 5 for the bf16 dtypes; 0, 1 otherwise), and takes the fewest groups
+ * within 3% of the fastest form.  For every group count within 10% of the
+ * fastest it then times each GEMM launch of the factorisation under each
+ * fixed policy and builds policy 3 from the fastest tile of each launch; the
+ * fewest groups within 3% of the fastest such form are kept if they beat the
+ * fixed form.  The choice, with policy 3's
  * per-launch tiles, is recorded in the JSON file cache_path (may be NULL)
  * under a key made of the GPU architecture, factor dtype, tile size t, p and
  * the largest tile-row count; a later call with the same key takes the

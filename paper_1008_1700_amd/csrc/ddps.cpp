@@ -93,6 +93,7 @@ struct ddps_ctx {
   double* d_val = nullptr;
   BlockInfo* d_blk = nullptr;
   void *d_tiles = nullptr, *d_spikes = nullptr, *d_scratch = nullptr;
+  bool spikes_zeroed = false;   // the whole spike array has been zeroed once (by an executed fill)
   void* d_tips = nullptr;   // spike tips packed row-major (rows of G^), 2(p-1) parts of t x 2t
   int tip_nseg = 0;         // > 0: reduced products on the packed tips (R <= 2 and 2t short enough)
   unsigned long long *d_colnorm = nullptr, *d_bad = nullptr, *d_band = nullptr;
@@ -394,9 +395,11 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
         sb.add_gemm(h->tile(i, 1, k - 1), t, h->tile(i, 2, k - 1), t, h->tile(i, 0, k), t, h->tile(i, 0, k), t,
                     t, t, t, G_NEG | G_A_UP | G_B_LO);
       if (i > 0) {
+        // the right-hand side of the left spike is nonzero in rows < 2t only
         if (k >= 1)
           sb.add_gemm(h->tile(i, 1, k - 1), t, h->spike(i, (int64_t)(k - 1) * t, 0), N,
-                      h->spike(i, (int64_t)k * t, 0), N, h->scr(i, 0), t, t, t, t, G_NEG | G_A_UP);
+                      (int64_t)k * t < 2 * (int64_t)t ? h->spike(i, (int64_t)k * t, 0) : nullptr, N, h->scr(i, 0), t,
+                      t, t, t, G_NEG | G_A_UP);
         else
           sb.add_copy(h->spike(i, 0, 0), N, h->scr(i, 0), t, t, t);
       }
@@ -510,11 +513,19 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
         const int N = (int)B.N, k = (int)B.T - 1 - s;
         const int c0 = i == 0 ? t : 0, c1 = i == p - 1 ? t : 2 * t;
         char* W = h->scr(i, 0) + (size_t)c0 * t * h->elt;
-        if (k < B.T - 1)
-          sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N, h->spike(i, (int64_t)k * t, c0), N,
-                      W, t, t, c1 - c0, t, G_NEG | G_A_LO);
-        else
+        if (k < B.T - 1) {
+          // left columns: W = G_k - U_{k,k+1} G_{k+1}; right columns: the
+          // forward sweep left them zero above the last tile row
+          const int cm = std::max(c0, t);
+          if (cm > c0)
+            sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N,
+                        h->spike(i, (int64_t)k * t, c0), N, W, t, t, cm - c0, t, G_NEG | G_A_LO);
+          if (c1 > cm)
+            sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, cm), N, nullptr, 0,
+                        h->scr(i, 0) + (size_t)cm * t * h->elt, t, t, c1 - cm, t, G_NEG | G_A_LO);
+        } else {
           sb.add_copy(h->spike(i, (int64_t)k * t, c0), N, W, t, t, c1 - c0);
+        }
       }
       sb.end(S);
       sb.begin(LK_GEMM);
@@ -729,13 +740,20 @@ int default_groups(const ddps_ctx* h) { return std::max(1, std::min(4, h->p / 8)
 // ---------------------------------------------------------------- phases
 int do_scatter(ddps_ctx* h, hipStream_t s) {
   const int64_t tcount = h->ntiles * (int64_t)h->t * h->t;
+  // Spikes: the first factorisation zeroes the whole array (the halves no
+  // block uses stay zero for good); later ones only the coupling parts that
+  // the scatter fills, since the sweeps write every other entry before it
+  // is read.  A fill recorded into a graph under capture has not run yet.
+  const bool whole = !h->spikes_zeroed;
   if (h->sdt == 0) {
     fill_f64((double*)h->d_tiles, tcount, 0.0, s);
-    fill_f64((double*)h->d_spikes, h->nspike, 0.0, s);
+    if (whole) fill_f64((double*)h->d_spikes, h->nspike, 0.0, s);
   } else {
     fill_f32((float*)h->d_tiles, tcount, 0.f, s);
-    fill_f32((float*)h->d_spikes, h->nspike, 0.f, s);
+    if (whole) fill_f32((float*)h->d_spikes, h->nspike, 0.f, s);
   }
+  if (!whole) zero_spike_rhs(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, s);
+  if (!h->capturing) h->spikes_zeroed = true;
   fill_u64(h->d_colnorm, (int64_t)h->p * 2 * h->t, 0ull, s);
   fill_u64(h->d_bad, 1, ~0ull, s);
   fill_f64(h->d_mask, h->m, 0.0, s);
@@ -1215,6 +1233,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->d_tiles = vp;
   if ((rc = h->alloc_raw(vp, (size_t)std::max<int64_t>(h->nspike, 1) * h->elt))) return fail(rc);
   h->d_spikes = vp;
+  h->spikes_zeroed = false;
   if (h->tip_nseg > 0) {
     if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
     h->d_tips = vp;
@@ -1964,12 +1983,17 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
   int rc;
   std::string modes;
   const bool hit = cache_lookup(cache_path, key, &bs, &bq, &bms, &modes);
+  // per-launch tiles tuned for group counts whose best fixed form is within
+  // 10% of the fastest one (filled only without a cache hit)
+  std::vector<int> cand;
   if (!hit) {
     // fewest stream groups within 3% of the fastest form: extra streams are
     // kept only for a clear gain (their launches then time as overlapping)
     std::vector<std::array<double, 3>> tried;   // groups, policy, ms
     double best = 1e300;
-    for (int q = 0; q <= (h->gdt >= 2 ? 2 : 1); ++q)
+    std::vector<int> pols = {0, 1};
+    if (h->gdt >= 2) pols = {0, 1, 2, 4, 5};
+    for (int q : pols)
       for (int g : {1, 2, 4, 8}) {
         if (g > h->p) continue;
         if ((rc = ddps_set_execution(h, g, 0, q))) return rc;
@@ -1987,6 +2011,12 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
         bq = (int)c[1];
         bms = c[2];
       }
+    for (int g : {1, 2, 4, 8}) {
+      double gb = 1e300;
+      for (auto& c : tried)
+        if ((int)c[0] == g) gb = std::min(gb, c[2]);
+      if (gb <= 1.10 * best) cand.push_back(g);
+    }
   }
   bool stored = false;
   if (hit && bq == 3 && !modes.empty()) {
@@ -1996,15 +2026,34 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
     if ((rc = ddps_set_execution(h, bs, 0, 3))) return rc;
     stored = h->mode_cursor == (int)modes.size();
   }
-  if (!hit || (bq == 3 && !stored)) {
-    // per-launch tile choice for the chosen group count: every factor GEMM
-    // launch is timed under each policy (same launch sequence), and takes
-    // the tile of the policy under which it ran fastest
+  if (hit && bq == 3 && !stored) {
+    // cached per-launch form whose tiles no longer fit: tune them again
     double ms3 = 0;
     if ((rc = tune_launch_modes(h, bs, &ms3))) return rc;
-    if (hit || ms3 < bms) {
+  } else if (!hit) {
+    // per-launch tile choice: every factor GEMM launch is timed under each
+    // policy (same launch sequence) and takes the tile of the policy under
+    // which it ran fastest.  Done for each candidate group count; the fewest
+    // groups within 3% of the fastest per-launch form win, if that beats the
+    // fixed form.
+    std::vector<std::pair<int, double>> per;
+    std::vector<std::vector<int8_t>> choice;
+    double best3 = 1e300;
+    for (int g : cand) {
+      double ms3 = 0;
+      if ((rc = tune_launch_modes(h, g, &ms3))) return rc;
+      per.push_back({g, ms3});
+      choice.push_back(h->mode_choice);
+      best3 = std::min(best3, ms3);
+    }
+    int pick = -1;
+    for (size_t i = 0; i < per.size(); ++i)
+      if (per[i].second <= 1.03 * best3 && (pick < 0 || per[i].first < per[pick].first)) pick = (int)i;
+    if (pick >= 0 && per[pick].second < bms) {
+      bs = per[pick].first;
       bq = 3;
-      if (!hit) bms = ms3;
+      bms = per[pick].second;
+      h->mode_choice = choice[pick];
     }
   }
   if (!hit || (bq == 3 && !stored)) {

@@ -161,6 +161,10 @@ void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
 void setup_row_thresh(int64_t n, int p, int64_t Np, const int64_t* part, const BlockInfo* blocks,
                       const int64_t* row_ptr, const int32_t* col, const double* val, double eps, double* thresh,
                       hipStream_t s);
+// zero the coupling (right-hand side) parts of every block's spikes, which
+// the scatter fills; the rest of the spike array is written by the
+// factorisation before it is read, once the whole array has been zeroed once
+void zero_spike_rhs(int dtype, int p, int t, const BlockInfo* blocks, void* spikes, hipStream_t s);
 void fill_f64(double* ptr, int64_t count, double v, hipStream_t s);
 void fill_f32(float* ptr, int64_t count, float v, hipStream_t s);
 void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipStream_t s);

@@ -88,6 +88,24 @@ __global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
     p[i] = v;
 }
 
+// Zero the parts of the spike array that the scatter fills with coupling
+// entries: in block i > 0 the rows [0, min(2t, N)) of the t left-coupling
+// columns, in block i < p-1 the last t rows of the t right-coupling columns.
+// Every other spike entry the factorisation reads is written by it first.
+template <typename T>
+__global__ void k_zero_spike_rhs(int p, int t, const BlockInfo* __restrict__ blocks, T* __restrict__ spikes) {
+  const int i = blockIdx.x;
+  const BlockInfo B = blocks[i];
+  T* G = spikes + B.goff;
+  const int64_t top_rows = min((int64_t)2 * t, B.N);
+  for (int j = blockIdx.y; j < 2 * t; j += gridDim.y) {
+    const bool top = j < t;
+    if (top ? i == 0 : i == p - 1) continue;
+    const int64_t r0 = top ? 0 : B.N - t, r1 = top ? top_rows : B.N;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) G[(int64_t)j * B.N + r] = T(0);
+  }
+}
+
 template <typename T>
 __global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ part,
                           const BlockInfo* __restrict__ blocks, const int64_t* __restrict__ row_ptr,
@@ -181,6 +199,13 @@ void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, c
   (void)part;
   const int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)nb), dim3(256), 0, s, n, row_ptr, col, val, nnz, band, flags);
+}
+
+void zero_spike_rhs(int dtype, int p, int t, const BlockInfo* blocks, void* spikes, hipStream_t s) {
+  if (p <= 1) return;
+  const dim3 g((unsigned)p, (unsigned)std::min(2 * t, 512));
+  if (dtype == 0) hipLaunchKernelGGL(k_zero_spike_rhs<double>, g, dim3(256), 0, s, p, t, blocks, (double*)spikes);
+  else hipLaunchKernelGGL(k_zero_spike_rhs<float>, g, dim3(256), 0, s, p, t, blocks, (float*)spikes);
 }
 
 void fill_f64(double* ptr, int64_t count, double v, hipStream_t s) {

@@ -378,7 +378,7 @@ def main():
     traffic, traffic_src = recorded_traffic(args.config, args.mode, k["launches_per_step"])
     roof = dict(bound="mfma", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                 frac=achieved / peak, traffic=traffic,
-                kernel="k_gemm_bf16 / k_gemm_std (grouped GEMM of stages 2 and 4)",
+                kernel="k_gemm_dl / k_gemm_bf16 / k_gemm_std (grouped GEMM of stages 2 and 4)",
                 launches_per_step=k["launches_per_step"], kernel_ms_per_step=kms,
                 stream_groups=res["exec"]["streams"], launch_timing=k.get("timing"),
                 avg_launch_us=kms * 1e3 / max(k["launches_per_step"], 1),

@@ -410,34 +410,60 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       if (k == B.T - 1 && i < p - 1) sb.add_copy(h->spike(i, (int64_t)k * t, t), N, h->scr(i, 3), t, t, t);
     }
     sb.end(S);
-    // LU of S_k, 64-column panels: panel LU (+ inverses of its 64 x 64
-    // triangles), column and row panels, trailing update
-    for (int j = 0; j < Q; ++j) {
-      const int j64 = j * 64, rest = t - (j + 1) * 64;
-      sb.begin(LK_PANEL);
-      for (int i : act) {
-        const BlockInfo& B = h->blk[i];
-        sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64,
-                     B.voff + (int64_t)k * t + j64);
+    // LU of S_k in 64-column panels (panel LU with the inverses of its 64 x 64
+    // triangles, then column and row panels), blocked in two levels: inside
+    // an outer panel of kOuter columns [J0, J1) each 64-column step updates
+    // only the rows of the outer panel (all columns to its right) and the
+    // columns of the outer panel (all rows below); the rest of the trailing
+    // matrix, rows and columns >= J1, takes the sum of those steps' products
+    // as one rank-(J1 - J0) update after the outer panel.  Same products as a
+    // rank-64 update per step, grouped so that the trailing matrix is read
+    // and written once per outer panel instead of once per step.
+    constexpr int kOuter = 256;
+    for (int J0 = 0; J0 < t; J0 += kOuter) {
+      const int J1 = std::min(t, J0 + kOuter);
+      for (int j64 = J0; j64 < J1; j64 += 64) {
+        const int rest = t - j64 - 64, w = J1 - j64 - 64;
+        sb.begin(LK_PANEL);
+        for (int i : act) {
+          const BlockInfo& B = h->blk[i];
+          sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64,
+                       B.voff + (int64_t)k * t + j64);
+        }
+        sb.end(S);
+        if (rest <= 0) continue;
+        sb.begin(LK_GEMM);
+        for (int i : act) {
+          char* D = h->tile(i, 0, k);
+          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
+                      rest, 64, 64, G_B_MUP | G_B_UP);
+          sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
+                      64, rest, 64, G_A_MLU | G_A_LO);
+        }
+        sb.end(S);
+        if (w <= 0) continue;
+        sb.begin(LK_GEMM);
+        for (int i : act) {
+          char* D = h->tile(i, 0, k);
+          // rows of the outer panel below this step, every column to the right
+          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
+                      h->sub(D, j64 + 64, j64 + 64), t, w, rest, 64, G_NEG);
+          // rows below the outer panel, columns of the outer panel
+          if (t > J1)
+            sb.add_gemm(h->sub(D, J1, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, J1, j64 + 64), t,
+                        h->sub(D, J1, j64 + 64), t, t - J1, w, 64, G_NEG);
+        }
+        sb.end(S);
       }
-      sb.end(S);
-      if (rest <= 0) continue;
-      sb.begin(LK_GEMM);
-      for (int i : act) {
-        char* D = h->tile(i, 0, k);
-        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
-                    rest, 64, 64, G_B_MUP | G_B_UP);
-        sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
-                    64, rest, 64, G_A_MLU | G_A_LO);
+      if (t > J1) {
+        sb.begin(LK_GEMM);
+        for (int i : act) {
+          char* D = h->tile(i, 0, k);
+          sb.add_gemm(h->sub(D, J1, J0), t, h->sub(D, J0, J1), t, h->sub(D, J1, J1), t, h->sub(D, J1, J1), t, t - J1,
+                      t - J1, J1 - J0, G_NEG);
+        }
+        sb.end(S);
       }
-      sb.end(S);
-      sb.begin(LK_GEMM);
-      for (int i : act) {
-        char* D = h->tile(i, 0, k);
-        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
-                    h->sub(D, j64 + 64, j64 + 64), t, rest, rest, 64, G_NEG);
-      }
-      sb.end(S);
     }
     // inverse triangles of the whole tile by recursive halving of the panel
     // range: for a split [lo, mid) | [mid, hi) whose halves are inverted,

@@ -93,6 +93,12 @@ struct ddps_ctx {
   double* d_val = nullptr;
   BlockInfo* d_blk = nullptr;
   void *d_tiles = nullptr, *d_spikes = nullptr, *d_scratch = nullptr;
+  // Off-diagonal factors L_{k+1,k}, U_{k,k+1} in storage of their own (when
+  // memory allows): the coupling tiles then keep A's entries, so the factor
+  // products read them in place instead of from copies.  lu_off[i] is block
+  // i's first tile in d_lu (its L tiles, then its U tiles).
+  void* d_lu = nullptr;
+  std::vector<int64_t> lu_off;
   bool spikes_zeroed = false;   // the whole spike array has been zeroed once (by an executed fill)
   void* d_tips = nullptr;   // spike tips packed row-major (rows of G^), 2(p-1) parts of t x 2t
   int tip_nseg = 0;         // > 0: reduced products on the packed tips (R <= 2 and 2t short enough)
@@ -180,6 +186,13 @@ struct ddps_ctx {
     const BlockInfo& B = blk[i];
     const int64_t idx = B.tiles + (which == 0 ? k : which == 1 ? B.T + k : 2 * B.T - 1 + k);
     return (char*)d_tiles + (size_t)idx * t * t * elt;
+  }
+  // L_{k+1,k} (which 1) or U_{k,k+1} (which 2) of block i
+  char* lu(int i, int which, int k) const {
+    if (!d_lu) return tile(i, which, k);
+    const BlockInfo& B = blk[i];
+    const int64_t idx = lu_off[i] + (which == 1 ? k : B.T - 1 + k);
+    return (char*)d_lu + (size_t)idx * t * t * elt;
   }
   char* sub(char* tile_base, int r, int c) const {  // element (r, c) of a t x t tile
     return tile_base + ((size_t)c * t + r) * elt;
@@ -392,18 +405,18 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       const BlockInfo& B = h->blk[i];
       const int N = (int)B.N;
       if (k >= 1)
-        sb.add_gemm(h->tile(i, 1, k - 1), t, h->tile(i, 2, k - 1), t, h->tile(i, 0, k), t, h->tile(i, 0, k), t,
+        sb.add_gemm(h->lu(i, 1, k - 1), t, h->lu(i, 2, k - 1), t, h->tile(i, 0, k), t, h->tile(i, 0, k), t,
                     t, t, t, G_NEG | G_A_UP | G_B_LO);
       if (i > 0) {
         // the right-hand side of the left spike is nonzero in rows < 2t only
         if (k >= 1)
-          sb.add_gemm(h->tile(i, 1, k - 1), t, h->spike(i, (int64_t)(k - 1) * t, 0), N,
+          sb.add_gemm(h->lu(i, 1, k - 1), t, h->spike(i, (int64_t)(k - 1) * t, 0), N,
                       (int64_t)k * t < 2 * (int64_t)t ? h->spike(i, (int64_t)k * t, 0) : nullptr, N, h->scr(i, 0), t,
                       t, t, t, G_NEG | G_A_UP);
         else
           sb.add_copy(h->spike(i, 0, 0), N, h->scr(i, 0), t, t, t);
       }
-      if (k < B.T - 1) {
+      if (k < B.T - 1 && !h->d_lu) {   // the factors overwrite the coupling tiles: copies of A's entries
         sb.add_copy(h->tile(i, 1, k), t, h->scr(i, 1), t, t, t);
         sb.add_copy(h->tile(i, 2, k), t, h->scr(i, 2), t, t, t);
       }
@@ -517,8 +530,10 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       const int N = (int)B.N;
       char* D = h->tile(i, 0, k);
       if (k < B.T - 1) {
-        sb.add_gemm(h->scr(i, 1), t, D, t, nullptr, 0, h->tile(i, 1, k), t, t, t, t, G_A_UP | G_B_MUP | G_B_UP);
-        sb.add_gemm(D, t, h->scr(i, 2), t, nullptr, 0, h->tile(i, 2, k), t, t, t, t, G_A_MLU | G_A_LO | G_B_LO);
+        const char* a_lo = h->d_lu ? h->tile(i, 1, k) : h->scr(i, 1);   // A_{k+1,k}
+        const char* a_up = h->d_lu ? h->tile(i, 2, k) : h->scr(i, 2);   // A_{k,k+1}
+        sb.add_gemm(a_lo, t, D, t, nullptr, 0, h->lu(i, 1, k), t, t, t, t, G_A_UP | G_B_MUP | G_B_UP);
+        sb.add_gemm(D, t, a_up, t, nullptr, 0, h->lu(i, 2, k), t, t, t, t, G_A_MLU | G_A_LO | G_B_LO);
       }
       if (i > 0) sb.add_gemm(D, t, h->scr(i, 0), t, nullptr, 0, h->spike(i, (int64_t)k * t, 0), N, t, t, t, G_A_MLU | G_A_LO);
       if (k == B.T - 1 && i < p - 1)
@@ -544,10 +559,10 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
           // forward sweep left them zero above the last tile row
           const int cm = std::max(c0, t);
           if (cm > c0)
-            sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N,
+            sb.add_gemm(h->lu(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N,
                         h->spike(i, (int64_t)k * t, c0), N, W, t, t, cm - c0, t, G_NEG | G_A_LO);
           if (c1 > cm)
-            sb.add_gemm(h->tile(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, cm), N, nullptr, 0,
+            sb.add_gemm(h->lu(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, cm), N, nullptr, 0,
                         h->scr(i, 0) + (size_t)cm * t * h->elt, t, t, c1 - cm, t, G_NEG | G_A_LO);
         } else {
           sb.add_copy(h->spike(i, (int64_t)k * t, c0), N, W, t, t, c1 - c0);
@@ -579,7 +594,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
       const BlockInfo& B = h->blk[i];
       if (B.T <= k) continue;
       GemvProb G{};
-      G.A = k >= 1 ? h->tile(i, 1, k - 1) : h->tile(i, 0, k);
+      G.A = k >= 1 ? h->lu(i, 1, k - 1) : h->tile(i, 0, k);
       G.lda = t;
       G.x1 = yp + B.voff + (int64_t)(k >= 1 ? k - 1 : 0) * t;
       G.x2 = G.x1;
@@ -621,7 +636,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
       if (B.T <= s) continue;
       const int k = (int)B.T - 1 - s;
       GemvProb G{};
-      G.A = k < B.T - 1 ? h->tile(i, 2, k) : h->tile(i, 0, k);
+      G.A = k < B.T - 1 ? h->lu(i, 2, k) : h->tile(i, 0, k);
       G.lda = t;
       G.x1 = yp + B.voff + (int64_t)(k < B.T - 1 ? k + 1 : k) * t;
       G.x2 = G.x1;
@@ -1254,7 +1269,19 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     budget = fr > ((size_t)1 << 30) ? fr - ((size_t)1 << 30) : fr;
   }
   if (need > budget) return fail(DDPS_E_NOMEM);
+  int64_t nlu = 0;
+  h->lu_off.assign(p, 0);
+  for (int i = 0; i < p; ++i) {
+    h->lu_off[i] = nlu;
+    nlu += 2 * (h->blk[i].T - 1);
+  }
+  const size_t lu_bytes = (size_t)nlu * t * t * h->elt;
+  const bool sep_lu = nlu > 0 && need + lu_bytes <= budget;
   void* vp;
+  if (sep_lu) {
+    if ((rc = h->alloc_raw(vp, lu_bytes))) return fail(rc);
+    h->d_lu = vp;
+  }
   if ((rc = h->alloc_raw(vp, (size_t)h->ntiles * t * t * h->elt))) return fail(rc);
   h->d_tiles = vp;
   if ((rc = h->alloc_raw(vp, (size_t)std::max<int64_t>(h->nspike, 1) * h->elt))) return fail(rc);
@@ -1775,7 +1802,7 @@ int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* 
   const BlockInfo& B = h->blk[blk];
   if (k < 0 || k >= B.T || (which > 0 && k >= B.T - 1)) return DDPS_E_ARG;
   const int64_t tt = (int64_t)h->t * h->t;
-  const char* src = h->tile(blk, which, k);
+  const char* src = which == 0 ? h->tile(blk, 0, k) : h->lu(blk, which, k);
   if (h->sdt == 0) {
     HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * tt, hipMemcpyDeviceToDevice, h->stream));
   } else {

@@ -46,6 +46,7 @@ struct Launch {
   double flops;
   double bytes;
   int mode;  // GEMM: tile mode; GEMV: 1 = every problem 16-byte aligned (wide loads)
+  int64_t ord = -1;  // GEMM: offset of its tile order in d_order, -1 for the plain order
 };
 
 struct TimingRec {
@@ -108,6 +109,7 @@ struct ddps_ctx {
   double* d_mask = nullptr;
   int64_t *d_c = nullptr, *d_rrow = nullptr;
   GemmProb* d_gemm = nullptr;
+  int32_t* d_order = nullptr;   // tile orders of the GEMM launches with uneven tiles
   PanelProb* d_panel = nullptr;
   GemvProb* d_gemv = nullptr;
   double *d_ypad = nullptr, *d_vpad = nullptr;
@@ -282,6 +284,8 @@ double gemm_prob_flops(const GemmProb& P, int BM, int BN) {
 struct ScheduleBuilder {
   ddps_ctx* h;
   std::vector<GemmProb> gemm;
+  std::vector<int32_t> order;   // tile orders (see tile_order)
+  int64_t cur_ord = -1;
   std::vector<PanelProb> panel;
   std::vector<GemvProb> gemv;
   // current launch
@@ -327,21 +331,59 @@ struct ScheduleBuilder {
       nwg += ((P.M + BM - 1) / BM) * ((P.N + BN - 1) / BN);
       flops += gemm_prob_flops(P, BM, BN);
     }
+    tile_order(BM, BN);
     return mode;
+  }
+  // Dispatch order of the launch's tiles.  The kernels map workgroup b to
+  // logical tile (b % 8) * (n / 8) + ... (a contiguous range per XCD, which
+  // the XCD's CUs take in order).  Where triangular operands make the tiles'
+  // K ranges unequal, each XCD's range is sorted longest first (stable), so
+  // the short tiles fill in at the end instead of a long one starting last;
+  // the XCD still gets the same tiles.  The kernel reads order[logical] for
+  // the tile to compute.  Plain launches keep the identity (cur_ord = -1).
+  void tile_order(int BM, int BN) {
+    cur_ord = -1;
+    bool tri = false;
+    for (size_t q = (size_t)off; q < gemm.size(); ++q)
+      tri = tri || (gemm[q].flags & (G_A_UP | G_A_LO | G_B_UP | G_B_LO));
+    if (!tri || nwg < 2) return;
+    std::vector<int32_t> klen(nwg);
+    for (size_t q = (size_t)off; q < gemm.size(); ++q) {
+      const GemmProb& P = gemm[q];
+      const int tm = (P.M + BM - 1) / BM, tn = (P.N + BN - 1) / BN;
+      for (int l = 0; l < tm * tn; ++l) {
+        const int I0 = (l % tm) * BM, J0 = (l / tm) * BN;
+        int kb = 0, ke = P.K;
+        if (P.flags & G_A_UP) kb = std::max(kb, I0);
+        if (P.flags & G_B_LO) kb = std::max(kb, J0);
+        if (P.flags & G_A_LO) ke = std::min(ke, I0 + BM);
+        if (P.flags & G_B_UP) ke = std::min(ke, J0 + BN);
+        klen[P.tile0 + l] = std::max(0, ke - kb);
+      }
+    }
+    cur_ord = (int64_t)order.size();
+    order.resize(order.size() + nwg);
+    int32_t* o = order.data() + cur_ord;
+    const int per = nwg >> 3, rem = nwg & 7;
+    for (int x = 0; x < 8; ++x) {
+      const int lo = x * per + std::min(x, rem), cnt = per + (x < rem ? 1 : 0);
+      for (int r = 0; r < cnt; ++r) o[lo + r] = lo + r;
+      std::stable_sort(o + lo, o + lo + cnt, [&](int32_t a, int32_t b) { return klen[a] > klen[b]; });
+    }
   }
   void end(std::vector<Launch>& out) {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
                                                                               : (int64_t)gemv.size()) - off;
     const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
     if (cnt > 0 && nwg > 0) {
-      out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode});
+      out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode, kind == LK_GEMM ? cur_ord : -1});
       if (kind == LK_GEMM) ++h->mode_cursor;
     }
   }
   Launch end_one() {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
     const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
-    return Launch{kind, off, (int)cnt, nwg, flops, bytes, mode};
+    return Launch{kind, off, (int)cnt, nwg, flops, bytes, mode, kind == LK_GEMM ? cur_ord : -1};
   }
   void add_gemm(const void* A, int lda, const void* B, int ldb, const void* C0, int ldc0, void* D, int ldd,
                 int M, int N, int K, int flags) {
@@ -754,7 +796,9 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
   hipEvent_t a;
   h->tim_begin(tkind, a, s);
   switch (L.kind) {
-    case LK_GEMM: launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, s); break;
+    case LK_GEMM:
+      launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, s, L.ord >= 0 ? h->d_order + L.ord : nullptr);
+      break;
     case LK_PANEL: launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, s); break;
     case LK_TIPMV:
       launch_tipmv(h->sdt, R, h->tip_nseg, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
@@ -880,18 +924,23 @@ int build_schedules(ddps_ctx* h) {
   h->sch_retr.clear();
   build_solve_schedules(h, sb);
   h->free_ptr(h->d_gemm);
+  h->free_ptr(h->d_order);
   h->free_ptr(h->d_panel);
   h->free_ptr(h->d_gemv);
   h->d_gemm = nullptr;
+  h->d_order = nullptr;
   h->d_panel = nullptr;
   h->d_gemv = nullptr;
   int rc;
-  if ((rc = h->alloc(h->d_gemm, (int64_t)sb.gemm.size())) || (rc = h->alloc(h->d_panel, (int64_t)sb.panel.size())) ||
+  if ((rc = h->alloc(h->d_gemm, (int64_t)sb.gemm.size())) || (rc = h->alloc(h->d_order, (int64_t)sb.order.size())) ||
+      (rc = h->alloc(h->d_panel, (int64_t)sb.panel.size())) ||
       (rc = h->alloc(h->d_gemv, (int64_t)sb.gemv.size())))
     return rc;
   hipStream_t s = h->stream;
   if (!sb.gemm.empty())
     HIPCHK(hipMemcpyAsync(h->d_gemm, sb.gemm.data(), sizeof(GemmProb) * sb.gemm.size(), hipMemcpyHostToDevice, s));
+  if (!sb.order.empty())
+    HIPCHK(hipMemcpyAsync(h->d_order, sb.order.data(), sizeof(int32_t) * sb.order.size(), hipMemcpyHostToDevice, s));
   if (!sb.panel.empty())
     HIPCHK(hipMemcpyAsync(h->d_panel, sb.panel.data(), sizeof(PanelProb) * sb.panel.size(), hipMemcpyHostToDevice, s));
   if (!sb.gemv.empty())

@@ -133,7 +133,10 @@ struct Coef3 {
 
 // Launch wrappers (kernels are in the .hip files).  `stream` is the handle's
 // stream; the problem arrays live in device memory.
-void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s);
+// order (device, may be null): logical tile of each workgroup slot, a
+// permutation of [0, nwg) (longest K range first within each XCD's range)
+void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s,
+                 const int32_t* order = nullptr);
 void gemm_tile_shape(int dtype, int mode, int* bm, int* bn);
 void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
                   unsigned long long* bad, hipStream_t s);

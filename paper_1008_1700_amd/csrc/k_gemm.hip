@@ -105,7 +105,8 @@ __device__ __forceinline__ TileCoord tile_of(const GemmProb& P, int wg) {
 // f64 / f32: K chunk 16, one MFMA 16x16x4 per (k4, mi, ni).
 // ------------------------------------------------------------------------
 template <typename T, int BM, int BN, int BK = 16, int OCC = 1>
-__global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restrict__ probs, int nprob,
+                                                 const int32_t* __restrict__ order) {
   constexpr int PADL = 4;
   constexpr int MB = BM / 32, NB = BN / 32;          // 16x16 blocks per wave
   constexpr int AE = BM * BK / 256, BE = BN * BK / 256;  // elements per thread
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
   __shared__ T Bs[2][BK][BN + PADL];
   using acc_t = typename Mma<T>::acc;
 
-  const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int wg = order ? order[xcd_swizzle(blockIdx.x, gridDim.x)] : xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
   const TileCoord tc = tile_of<BM, BN>(P, wg);
   const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
@@ -287,7 +288,8 @@ __device__ __forceinline__ void store_tile32(const GemmProb& P, const f32x16 (&a
 }
 
 template <bool SPLIT, int BM, int BN, int OCC = 1, int ST = 1, int BK = 32, int NW = 4>
-__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __restrict__ probs, int nprob,
+                                                 const int32_t* __restrict__ order) {
   // NW waves in a 2 x NW/2 arrangement, wave tile BM/2 x 2BN/NW of 32 x 32 blocks
   constexpr int NT = 64 * NW;
   constexpr int LDK = BK + 8;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
   __shared__ __attribute__((aligned(16))) __bf16 As[ST][NS][BM][LDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][NS][BN][LDK];
 
-  const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int wg = order ? order[xcd_swizzle(blockIdx.x, gridDim.x)] : xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
   const TileCoord tc = tile_of<BM, BN>(P, wg);
   const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
@@ -571,7 +573,8 @@ __device__ __forceinline__ void dl_chunk(const float* __restrict__ ca, const flo
 }
 
 template <bool SPLIT, int BM, int BN, int NW, int OCC>
-__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __restrict__ probs, int nprob,
+                                                 const int32_t* __restrict__ order) {
   constexpr int BK = 32;
   constexpr int MB = BM / 64, NB = BN / (16 * NW);
   constexpr int NA = BK * BM / 256 / NW;   // A instructions per wave and chunk
@@ -583,7 +586,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __rest
   __shared__ __attribute__((aligned(16))) float As[2][BK * BM];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN * BK];
 
-  const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int wg = order ? order[xcd_swizzle(blockIdx.x, gridDim.x)] : xcd_swizzle(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprob, wg)];
   const TileCoord tc = tile_of<BM, BN>(P, wg);
   const int I0 = tc.I0, J0 = tc.J0, kb = tc.kb, ke = tc.ke;
@@ -660,41 +663,42 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __rest
 // mode: 0 = 64 x 64 tiles, 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (bf16 only),
 // 3 = 128 x 128 tiles with direct LDS loads (bf16 only; otherwise as 1),
 // 4 = 256 x 256 tiles on 8 waves with direct LDS loads (bf16 only; otherwise as 1)
-void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s) {
+void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg, hipStream_t s,
+                 const int32_t* order) {
   if (nwg <= 0 || nprob <= 0) return;
   const dim3 g(nwg), b(256);
   // two workgroups per CU (two waves per SIMD) measured best for f64/f32
   if (dtype <= 1) {
     if (mode >= 1) {
-      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 128, 128, 16, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_std<float, 128, 128, 16, 2>), g, b, 0, s, probs, nprob);
+      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 128, 128, 16, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_std<float, 128, 128, 16, 2>), g, b, 0, s, probs, nprob, order);
     } else {
-      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 64, 64, 16, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_std<float, 64, 64, 16, 2>), g, b, 0, s, probs, nprob);
+      if (dtype == 0) hipLaunchKernelGGL((k_gemm_std<double, 64, 64, 16, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_std<float, 64, 64, 16, 2>), g, b, 0, s, probs, nprob, order);
     }
     return;
   }
   const bool split = dtype == 2;
   switch (mode) {
     case 4:
-      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_dl<false, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_dl<false, 256, 256, 8, 1>), g, dim3(512), 0, s, probs, nprob, order);
       break;
     case 3:
-      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 128, 128, 4, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_dl<false, 128, 128, 4, 2>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_dl<true, 128, 128, 4, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_dl<false, 128, 128, 4, 2>), g, b, 0, s, probs, nprob, order);
       break;
     case 2:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128, 1, 2>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 256, 128, 1, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 256, 128, 1, 2>), g, b, 0, s, probs, nprob, order);
       break;
     case 1:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 128, 128, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 128, 128, 2>), g, b, 0, s, probs, nprob, order);
       break;
     default:
-      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 64, 64, 2>), g, b, 0, s, probs, nprob);
-      else hipLaunchKernelGGL((k_gemm_bf16<false, 64, 64, 2>), g, b, 0, s, probs, nprob);
+      if (split) hipLaunchKernelGGL((k_gemm_bf16<true, 64, 64, 2>), g, b, 0, s, probs, nprob, order);
+      else hipLaunchKernelGGL((k_gemm_bf16<false, 64, 64, 2>), g, b, 0, s, probs, nprob, order);
       break;
   }
 }

@@ -1,11 +1,13 @@
 // Grouped GEMM on CDNA4 matrix cores: D = C0 +/- op(A) op(B) over a list of
 // independent problems (one launch covers every block of the partition).
 //
-// Workgroup tile BM x BN (64 x 64 or 128 x 128), 256 threads = 4 waves in a
-// 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA
-// blocks.  K advances in chunks (16 for f64/f32, 32 for bf16) staged through
-// LDS, with the next chunk's global loads in flight while the current chunk
-// is multiplied.  Operands are column-major (LAPACK layout); M and N need
+// Three kernels: k_gemm_std (f64 / f32 MFMA 16x16x4), k_gemm_bf16 (bf16 MFMA
+// on FP32 operands staged through registers) and k_gemm_dl (the same bf16
+// products with the operands copied straight into LDS).  For k_gemm_std the
+// workgroup tile is BM x BN (64 x 64 or 128 x 128), 256 threads = 4 waves in
+// a 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA
+// blocks; K advances in chunks of 16 staged through LDS, with the next
+// chunk's global loads in flight while the current chunk is multiplied.  Operands are column-major (LAPACK layout); M and N need
 // only be multiples of 64 (a 128-tile on the edge is masked).  Triangular
 // operands are exploited twice: the K range of each output tile is clipped
 // to where both operands can be nonzero, and masked loads read the

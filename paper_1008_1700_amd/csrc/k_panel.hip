@@ -19,9 +19,9 @@
 // do not depend on the split.
 //
 // Inversion, with the factors in LDS (row-major, L below the diagonal, U on
-// and above it); wave 0 forms Y = U^{-1} and wave 1 X = L^{-1} at the same
-// time, each with lane r computing row r one 16-column block at a time and
-// the earlier blocks' rows in LDS:
+// and above it); waves 0 and 2 form Y = U^{-1} and waves 1 and 3 X = L^{-1}
+// at the same time, lane r computing row r one 16-column block at a time
+// (each wave 8 of its columns) with the earlier blocks' rows in LDS:
 //   Y = U^{-1}, blocks left to right:
 //       Y(r,r) = 1/u(r,r),  Y(r,j) = -( sum_{r<=l<j} Y(r,l) U(l,j) ) / u(j,j),  j > r
 //   X = L^{-1}, blocks right to left (unit diagonal implied, not stored):
@@ -113,23 +113,47 @@ __global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ pro
     const double av = fabs((double)LU[r][r]);
     if (!(av > th) || !(av <= 1.7e308))
       atomicMin(bad, ((unsigned long long)P.block << 40) | (unsigned long long)(P.row0 + r));
-  } else if (w == 0) {
-    // Y = U^{-1}, 16-column blocks left to right
+  }
+
+  // Inversions, four rounds on all four waves: round b takes block 16b of
+  // Y = U^{-1} (waves 0 and 2) and block 48 - 16b of X = L^{-1} (waves 1
+  // and 3).  Each wave sums the earlier (Y) or later (X) blocks' terms for 8
+  // of the 16 columns.  Within a block, Y's columns depend on those to their
+  // left and X's on those to their right: wave 0 finishes Y's left half and
+  // wave 3 X's right half first; after a barrier wave 2 and wave 1 finish
+  // the other halves with those from LDS.  Every entry takes the terms in
+  // the same order as a one-wave inversion.
+  constexpr int kH = kB / 2;
+  const bool isY = (w & 1) == 0;
+  const int h0 = (w == 0 || w == 1) ? 0 : kH;   // first column of this wave's half
 #pragma unroll 1
-    for (int j0 = 0; j0 < kN; j0 += kB) {
-      T acc[kB];
+  for (int b = 0; b < kN / kB; ++b) {
+    const int j0 = isY ? kB * b : kN - kB - kB * b;
+    T acc[kH];
+    if (isY) {
 #pragma unroll
-      for (int jj = 0; jj < kB; ++jj) acc[jj] = T(0);
-      // earlier columns: Y(r, l) for l < j0 from LDS (zero for l < r)
+      for (int jj = 0; jj < kH; ++jj) acc[jj] = T(0);
 #pragma unroll 4
       for (int l = 0; l < j0; ++l) {
         const T yl = Wy[r][l];
 #pragma unroll
-        for (int jj = 0; jj < kB; ++jj) acc[jj] += yl * LU[l][j0 + jj];
+        for (int jj = 0; jj < kH; ++jj) acc[jj] += yl * LU[l][j0 + h0 + jj];
       }
-      T y[kB];
+    } else {
 #pragma unroll
-      for (int jj = 0; jj < kB; ++jj) {
+      for (int jj = 0; jj < kH; ++jj) acc[jj] = j0 + h0 + jj < r ? LU[r][j0 + h0 + jj] : T(0);
+#pragma unroll 4
+      for (int l = j0 + kB; l < kN; ++l) {
+        const T xl = Wx[r][l];
+#pragma unroll
+        for (int jj = 0; jj < kH; ++jj) acc[jj] += xl * LU[l][j0 + h0 + jj];
+      }
+    }
+    // first halves: Y's left (wave 0), X's right (wave 3)
+    if (w == 0) {
+      T y[kH];
+#pragma unroll
+      for (int jj = 0; jj < kH; ++jj) {
         const int j = j0 + jj;
         T s = acc[jj];
 #pragma unroll
@@ -138,42 +162,60 @@ __global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ pro
         y[jj] = j < r ? T(0) : (j == r ? rv : -s * rv);
       }
 #pragma unroll
-      for (int jj = 0; jj < kB; ++jj) Wy[r][j0 + jj] = y[jj];
-    }
-    // U^{-1} on and above the diagonal
-#pragma unroll 4
-    for (int c = 0; c < kN; ++c)
-      if (c >= r) D[c * ld + r] = Wy[r][c];
-  } else if (w == 1) {
-    // X = L^{-1}, 16-column blocks right to left
-#pragma unroll 1
-    for (int j0 = kN - kB; j0 >= 0; j0 -= kB) {
-      T acc[kB];
+      for (int jj = 0; jj < kH; ++jj) Wy[r][j0 + jj] = y[jj];
+    } else if (w == 3) {
+      T x[kH];
 #pragma unroll
-      for (int jj = 0; jj < kB; ++jj) acc[jj] = j0 + jj < r ? LU[r][j0 + jj] : T(0);
-      // later columns: X(r, l) for l >= j0 + 16 from LDS (zero for l >= r)
-#pragma unroll 4
-      for (int l = j0 + kB; l < kN; ++l) {
-        const T xl = Wx[r][l];
-#pragma unroll
-        for (int jj = 0; jj < kB; ++jj) acc[jj] += xl * LU[l][j0 + jj];
-      }
-      T x[kB];
-#pragma unroll
-      for (int jj = kB - 1; jj >= 0; --jj) {
-        const int j = j0 + jj;
+      for (int jj = kH - 1; jj >= 0; --jj) {
+        const int j = j0 + kH + jj;
         T s = acc[jj];
 #pragma unroll
-        for (int ll = jj + 1; ll < kB; ++ll) s += x[ll] * LU[j0 + ll][j];
+        for (int ll = jj + 1; ll < kH; ++ll) s += x[ll] * LU[j0 + kH + ll][j];
         x[jj] = j < r ? -s : T(0);
       }
 #pragma unroll
-      for (int jj = 0; jj < kB; ++jj) Wx[r][j0 + jj] = x[jj];
+      for (int jj = 0; jj < kH; ++jj) Wx[r][j0 + kH + jj] = x[jj];
     }
-    // L^{-1} strictly below the diagonal
+    __syncthreads();
+    // second halves, with the first halves from LDS
+    if (w == 2) {
+      T y[kH];
+#pragma unroll
+      for (int jj = 0; jj < kH; ++jj) {
+        const int j = j0 + kH + jj;
+        T s = acc[jj];
+#pragma unroll
+        for (int ll = 0; ll < kH; ++ll) s += Wy[r][j0 + ll] * LU[j0 + ll][j];
+#pragma unroll
+        for (int ll = 0; ll < jj; ++ll) s += y[ll] * LU[j0 + kH + ll][j];
+        const T rv = Rv[j];
+        y[jj] = j < r ? T(0) : (j == r ? rv : -s * rv);
+      }
+#pragma unroll
+      for (int jj = 0; jj < kH; ++jj) Wy[r][j0 + kH + jj] = y[jj];
+    } else if (w == 1) {
+      T x[kH];
+#pragma unroll
+      for (int jj = kH - 1; jj >= 0; --jj) {
+        const int j = j0 + jj;
+        T s = acc[jj];
+#pragma unroll
+        for (int ll = jj + 1; ll < kH; ++ll) s += x[ll] * LU[j0 + ll][j];
+#pragma unroll
+        for (int ll = kH; ll < kB; ++ll) s += Wx[r][j0 + ll] * LU[j0 + ll][j];
+        x[jj] = j < r ? -s : T(0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < kH; ++jj) Wx[r][j0 + jj] = x[jj];
+    }
+    __syncthreads();
+  }
+  // U^{-1} on and above the diagonal, L^{-1} strictly below it: each wave
+  // writes 16 of the 64 columns
 #pragma unroll 4
-    for (int c = 0; c < kN; ++c)
-      if (c < r) D[c * ld + r] = Wx[r][c];
+  for (int cc = 0; cc < kB; ++cc) {
+    const int c = kB * w + cc;
+    D[c * ld + r] = c >= r ? Wy[r][c] : Wx[r][c];
   }
 }
 

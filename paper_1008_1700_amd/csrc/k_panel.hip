@@ -1,18 +1,18 @@
 // Diagonal sub-tile kernel of the tile LU: for each problem, one workgroup of
-// four waves factors a 64 x 64 sub-tile without pivoting (A = L U, L unit
+// eight waves factors a 64 x 64 sub-tile without pivoting (A = L U, L unit
 // lower), then inverts both triangles and writes back L^{-1} strictly below
 // the diagonal and U^{-1} on and above it.
 //
 // The kernel is latency bound (a few of them run at a time, one per block of
-// the partition), so the work of one sub-tile is spread over four waves.
+// the partition), so the work of one sub-tile is spread over eight waves.
 //
-// Elimination.  Wave w owns columns 16w .. 16w+15: lane r holds
-// a[c] = A(r, 16w + c) in registers.  In round b the wave owning columns
-// 16b .. 16b+15 runs their 16 elimination steps k: it reads the pivot u(k,k)
+// Elimination.  Wave w owns columns 8w .. 8w+7: lane r holds
+// a[c] = A(r, 8w + c) in registers.  In round b the wave owning columns
+// 8b .. 8b+7 runs their 8 elimination steps k: it reads the pivot u(k,k)
 // from lane k (v_readlane), forms the multipliers l(r) = a(r,k) / u(k,k) for
 // r > k, keeps them as column k of L, updates its own columns right of k and
 // puts the multipliers in LDS.  After one barrier every wave right of it
-// applies the same 16 steps to its columns, a(r,c) -= l(r) a(k,c), with the
+// applies the same 8 steps to its columns, a(r,c) -= l(r) a(k,c), with the
 // pivot row read from lane k of its own registers.  The multipliers of
 // consecutive rounds alternate between two LDS buffers.  The operations and
 // their order per entry are those of a one-wave elimination, so the factors
@@ -20,8 +20,9 @@
 //
 // Inversion, with the factors in LDS (row-major, L below the diagonal, U on
 // and above it); waves 0 and 2 form Y = U^{-1} and waves 1 and 3 X = L^{-1}
-// at the same time, lane r computing row r one 16-column block at a time
-// (each wave 8 of its columns) with the earlier blocks' rows in LDS:
+// at the same time (waves 4-7 only meet the barriers), lane r computing row
+// r one 16-column block at a time (each wave 8 of its columns) with the
+// earlier blocks' rows in LDS:
 //   Y = U^{-1}, blocks left to right:
 //       Y(r,r) = 1/u(r,r),  Y(r,j) = -( sum_{r<=l<j} Y(r,l) U(l,j) ) / u(j,j),  j > r
 //   X = L^{-1}, blocks right to left (unit diagonal implied, not stored):
@@ -40,7 +41,9 @@ namespace ddps {
 namespace {
 
 constexpr int kN = kTile;      // 64
-constexpr int kB = 16;         // column block
+constexpr int kB = 16;         // column block of the inversions
+constexpr int kW = 8;          // waves of the workgroup
+constexpr int kE = kN / kW;    // columns per wave in the elimination
 constexpr int kLdLU = kN + 4;  // row-major LU: 16-byte aligned 16-column pieces
 constexpr int kLdR = kN + 1;   // per-lane rows: conflict-free column access
 
@@ -58,54 +61,54 @@ __device__ __forceinline__ double lane_value(double x, int lane) {
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ probs,
+__global__ __launch_bounds__(64 * kW) void k_panel(const PanelProb* __restrict__ probs,
                                                const double* __restrict__ thresh,
                                                unsigned long long* __restrict__ bad) {
   __shared__ __attribute__((aligned(16))) T LU[kN][kLdLU];  // L (c < r) and U (c >= r), row-major
   __shared__ T Wy[kN][kLdR];                               // rows of U^{-1}
   __shared__ T Wx[kN][kLdR];                               // rows of L^{-1}
   __shared__ T Rv[kN];                                     // 1 / u(k, k)
-  __shared__ T Lm[2][kB][kN];                              // multipliers of the current 16 steps
+  __shared__ T Lm[2][kE][kN];                              // multipliers of the current round
   const PanelProb P = probs[blockIdx.x];
   T* __restrict__ D = (T*)P.D;
   const int r = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ld = P.ld;
 
-  T a[kB];   // a[c] = A(r, 16 w + c)
+  T a[kE];   // a[c] = A(r, kE w + c)
 #pragma unroll
-  for (int c = 0; c < kB; ++c) a[c] = D[(int64_t)(kB * w + c) * ld + r];
+  for (int c = 0; c < kE; ++c) a[c] = D[(int64_t)(kE * w + c) * ld + r];
 
 #pragma unroll 1
-  for (int kb = 0; kb < kN / kB; ++kb) {
-    // the owner eliminates its 16 columns and publishes their multipliers
+  for (int kb = 0; kb < kW; ++kb) {
+    // the owner eliminates its kE columns and publishes their multipliers
     if (w == kb) {
 #pragma unroll
-      for (int kc = 0; kc < kB; ++kc) {
-        const int k = kB * kb + kc;
+      for (int kc = 0; kc < kE; ++kc) {
+        const int k = kE * kb + kc;
         const T rp = T(1) / lane_value(a[kc], k);
         if (r == 0) Rv[k] = rp;
         const T l = r > k ? a[kc] * rp : T(0);
         a[kc] = r > k ? l : a[kc];
         Lm[kb & 1][kc][r] = l;
 #pragma unroll
-        for (int c = kc + 1; c < kB; ++c) a[c] -= l * lane_value(a[c], k);
+        for (int c = kc + 1; c < kE; ++c) a[c] -= l * lane_value(a[c], k);
       }
     }
     __syncthreads();
-    // the waves right of it apply the 16 steps to their columns
+    // the waves right of it apply the same steps to their columns
     if (w > kb) {
 #pragma unroll
-      for (int kc = 0; kc < kB; ++kc) {
-        const int k = kB * kb + kc;
+      for (int kc = 0; kc < kE; ++kc) {
+        const int k = kE * kb + kc;
         const T l = Lm[kb & 1][kc][r];
 #pragma unroll
-        for (int c = 0; c < kB; ++c) a[c] -= l * lane_value(a[c], k);
+        for (int c = 0; c < kE; ++c) a[c] -= l * lane_value(a[c], k);
       }
     }
   }
 #pragma unroll
-  for (int c = 0; c < kB; ++c) LU[r][kB * w + c] = a[c];
+  for (int c = 0; c < kE; ++c) LU[r][kE * w + c] = a[c];
   __syncthreads();
 
   if (w == 2) {
@@ -130,7 +133,8 @@ __global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ pro
   for (int b = 0; b < kN / kB; ++b) {
     const int j0 = isY ? kB * b : kN - kB - kB * b;
     T acc[kH];
-    if (isY) {
+    if (w >= 4) {
+    } else if (isY) {
 #pragma unroll
       for (int jj = 0; jj < kH; ++jj) acc[jj] = T(0);
 #pragma unroll 4
@@ -211,10 +215,10 @@ __global__ __launch_bounds__(256) void k_panel(const PanelProb* __restrict__ pro
     __syncthreads();
   }
   // U^{-1} on and above the diagonal, L^{-1} strictly below it: each wave
-  // writes 16 of the 64 columns
-#pragma unroll 4
-  for (int cc = 0; cc < kB; ++cc) {
-    const int c = kB * w + cc;
+  // writes kE of the 64 columns
+#pragma unroll
+  for (int cc = 0; cc < kE; ++cc) {
+    const int c = kE * w + cc;
     D[c * ld + r] = c >= r ? Wy[r][c] : Wx[r][c];
   }
 }
@@ -223,9 +227,9 @@ void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* th
                   unsigned long long* bad, hipStream_t s) {
   if (nprob <= 0) return;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_panel<double>, dim3(nprob), dim3(256), 0, s, probs, thresh, bad);
+    hipLaunchKernelGGL(k_panel<double>, dim3(nprob), dim3(64 * kW), 0, s, probs, thresh, bad);
   else
-    hipLaunchKernelGGL(k_panel<float>, dim3(nprob), dim3(256), 0, s, probs, thresh, bad);
+    hipLaunchKernelGGL(k_panel<float>, dim3(nprob), dim3(64 * kW), 0, s, probs, thresh, bad);
 }
 
 }  // namespace ddps

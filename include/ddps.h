@@ -227,7 +227,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
 /* Autotuner of the execution form.  It times ddps_factor on the device for
- * stream groups {1, 2, 4, 8} (at most p) and the fixed tile policies (0, 1,
+ * stream groups {1, 2, 3, 4, 6, 8} (at most p) and the fixed tile policies (0, 1,
  * 2, 4, 5 for the bf16 dtypes; 0, 1 otherwise), and takes the fewest groups
  * within 3% of the fastest form.  For every group count within 10% of the
  * fastest it then times each GEMM launch of the factorisation under each

@@ -2096,7 +2096,7 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
     std::vector<int> pols = {0, 1};
     if (h->gdt >= 2) pols = {0, 1, 2, 4, 5};
     for (int q : pols)
-      for (int g : {1, 2, 4, 8}) {
+      for (int g : {1, 2, 3, 4, 6, 8}) {
         if (g > h->p) continue;
         if ((rc = ddps_set_execution(h, g, 0, q))) return rc;
         if ((rc = ddps_factor(h))) return rc;       // warm-up
@@ -2113,7 +2113,7 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
         bq = (int)c[1];
         bms = c[2];
       }
-    for (int g : {1, 2, 4, 8}) {
+    for (int g : {1, 2, 3, 4, 6, 8}) {
       double gb = 1e300;
       for (auto& c : tried)
         if ((int)c[0] == g) gb = std::min(gb, c[2]);

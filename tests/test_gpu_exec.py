@@ -92,7 +92,7 @@ def test_autotune_and_cache(tmp_path):
     S = make_solver(d, inner_tol=1e-13)
     try:
         r1 = ddps.ddps_autotune(S.h, str(cache))
-        assert r1["streams"] in (1, 2, 4) and r1["tile_policy"] in (0, 1, 3) and r1["factor_ms"] > 0
+        assert r1["streams"] in (1, 2, 3, 4, 6) and r1["tile_policy"] in (0, 1, 3) and r1["factor_ms"] > 0
         x, info = _solve(S, d)
         assert info.relres_inf <= 1e-12
         data = json.loads(cache.read_text())

@@ -200,6 +200,28 @@ def test_c1_solve_many(c1, c1_solver):
         assert relerr(host(Xd)[j], host(x1)) <= 1e-11
 
 
+def test_zero_right_hand_side(c1, c1_solver):
+    """f = 0 meets any relative tolerance on entry: x stays exactly zero and
+    no preconditioner application runs.  As one column of a block of
+    right-hand sides it stays zero while the other column is solved."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    A = c1["A"]
+    x = dev_vec(np.zeros(A.n))
+    rc, info = c1_solver.solve(dev_vec(np.zeros(A.n)), x, 1e-12)
+    assert rc == 0
+    assert info.applications == 0
+    assert not np.any(host(x))
+    F = np.stack([c1["f"], np.zeros(A.n)])
+    Fd = dev_vec(F)
+    Xd = torch.zeros_like(Fd)
+    rc, info = ddps.ddps_solve_many(c1_solver.h, Fd, Xd, 1e-12)
+    assert rc == 0
+    X = host(Xd)
+    assert not np.any(X[1])
+    assert relerr(X[0], c1["x_star"]) <= 1e-9
+
+
 @pytest.mark.parametrize("sizes,b,seed", [
     ([300], 20, 1),                      # p = 1, padded single block
     ([150, 201, 170], 5, 2),             # pad 42 / 55 / 22 rows, t = 64

@@ -101,7 +101,8 @@ def test_autotune_and_cache(tmp_path):
         assert key.startswith("gfx950/f64/t64/p7/") and val["streams"] == r1["streams"]
         r2 = ddps.ddps_autotune(S.h, str(cache))       # from the cache, no timing
         assert (r2["streams"], r2["tile_policy"]) == (r1["streams"], r1["tile_policy"])
-        assert r2["factor_ms"] == pytest.approx(r1["factor_ms"], rel=1e-3)
+        # the cache keeps the time in whole microseconds
+        assert r2["factor_ms"] == pytest.approx(r1["factor_ms"], abs=0.6e-3)
     finally:
         S.close()
 

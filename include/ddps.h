@@ -69,9 +69,7 @@ typedef struct {
   int32_t inner_maxit;     /* maximum inner iterations */
   int32_t outer_maxit;     /* maximum outer iterations (Section 4 uses 1000) */
   int32_t outer_method;    /* 0 = preconditioned BiCGStab (Section 4), 1 = iterative refinement
-                              x += P^{-1}(f - Ax); under refinement a step's inner tolerance is
-                              raised (up to 1e-2) to 0.1 tol ||f|| / ||r|| and to 0.1 of the
-                              previous step's residual ratio, never below inner_tol */
+                              x += P^{-1}(f - Ax) */
   int32_t guess;           /* 0: reduced solve starts at z^ = 0; 1: from the vector given to
                               ddps_set_guess (kept until replaced) */
   int32_t use_x0;          /* 1: x is read as the initial outer iterate */

@@ -1521,21 +1521,13 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
     return DDPS_OK;
   };
   if (h->opt.outer_method == 1) {
-    // iterative refinement: x += P^{-1} (f - A x).  When the previous step
-    // cut the residual only by a factor rho far above the inner tolerance
-    // (the low-precision factors, not the inner solve, limit the step), the
-    // next inner solve is asked for 0.1 rho instead: solving it further
-    // would not lower the outer residual.
-    double rho = 0.0;   // largest ||r_new|| / ||r_old|| of the previous step
-    std::vector<double> rprev;
+    // iterative refinement: x += P^{-1} (f - A x)
     while (!all_conv(rinf) && outer < h->opt.outer_maxit) {
       double worst = 0.0;   // largest ||r||/||f|| still above the tolerance
       for (int j = 0; j < k; ++j)
         if (fnorm[j] > 0) worst = std::max(worst, rinf[j] / fnorm[j]);
-      itol = std::max(h->opt.inner_tol, 0.1 * rho);
-      if (worst > 0) itol = std::max(itol, 0.1 * tol / worst);
-      itol = std::min(itol, std::max(h->opt.inner_tol, 1e-2));
-      rprev = rinf;
+      itol = h->opt.inner_tol;
+      if (worst > 0) itol = std::min(1e-2, std::max(itol, 0.1 * tol / worst));
       if ((rc = papply(h->d_ro, h->d_z))) return rc;
       // columns already converged keep their x
       Coef3 cf{};
@@ -1545,9 +1537,6 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       }
       lincomb(R, n, cf, h->d_xo, h->d_z, nullptr, h->d_xo, s);
       if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
-      rho = 0.0;
-      for (int j = 0; j < k; ++j)
-        if (rprev[j] > 0 && !conv_col(j, rprev[j])) rho = std::max(rho, rinf[j] / rprev[j]);
       outer += 1;
     }
   } else {

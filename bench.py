@@ -72,6 +72,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         f = torch.from_numpy(np.ascontiguousarray(fh.T)).cuda()        # row j = right-hand side j
         x = torch.zeros(k, A.n, dtype=torch.float64, device="cuda")
     val = S.val
+    log(f"{mode}: setup done, n={A.n}")
     if exec_form is None:
         tune = ddps.ddps_autotune(S.h, tune_cache)   # execution form (stream groups, tiles), untimed
     else:
@@ -85,6 +86,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
             return S.solve(f, x, tol, check=False)
         return ddps.ddps_solve_many(S.h, f, x, tol, check=False)
 
+    log(f"{mode}: execution form {tune}")
     for _ in range(warmup):
         step()
     infos = []
@@ -94,6 +96,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         infos.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"{mode}: {steps} timed steps, {(t1 - t0) * 1e3 / steps:.1f} ms each")
     rc, info = infos[-1]
     xs = x.cpu().numpy()
     # one more (untimed) step with every factor GEMM launch timed by HIP events

@@ -69,7 +69,12 @@ typedef struct {
   int32_t inner_maxit;     /* maximum inner iterations */
   int32_t outer_maxit;     /* maximum outer iterations (Section 4 uses 1000) */
   int32_t outer_method;    /* 0 = preconditioned BiCGStab (Section 4), 1 = iterative refinement
-                              x += P^{-1}(f - Ax) */
+                              x += P^{-1}(f - Ax).  Under refinement a step's inner tolerance is
+                              never below inner_tol; it is raised to 0.1 tol ||f|| / ||r|| (at
+                              most 1e-2), and to 0.1 rho when a step at inner_tol cut the
+                              residual by a ratio rho <= 1e-2 (the factors, not the inner solve,
+                              then limit the steps; stopped once a loosened step cuts it by less
+                              than 10 rho) */
   int32_t guess;           /* 0: reduced solve starts at z^ = 0; 1: from the vector given to
                               ddps_set_guess (kept until replaced) */
   int32_t use_x0;          /* 1: x is read as the initial outer iterate */

@@ -1521,13 +1521,26 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
     return DDPS_OK;
   };
   if (h->opt.outer_method == 1) {
-    // iterative refinement: x += P^{-1} (f - A x)
+    // iterative refinement: x += P^{-1} (f - A x).
+    // rho_f is the residual ratio of the last step whose inner solve was not
+    // loosened by rho_f itself.  When it is at most 1e-2 but far above
+    // inner_tol, the factors (not the inner solve) limit a step, and later
+    // steps ask the inner solve for 0.1 rho_f only.  Such a step never
+    // updates rho_f, and if it cuts the residual by less than 10 rho_f the
+    // loosening stops for the rest of the solve; so every loosened step still
+    // cuts the residual at least tenfold.
+    double rho_f = -1.0;
+    bool loosen_off = false;
+    std::vector<double> rprev;
     while (!all_conv(rinf) && outer < h->opt.outer_maxit) {
       double worst = 0.0;   // largest ||r||/||f|| still above the tolerance
       for (int j = 0; j < k; ++j)
         if (fnorm[j] > 0) worst = std::max(worst, rinf[j] / fnorm[j]);
       itol = h->opt.inner_tol;
+      const bool loosened = !loosen_off && rho_f > 0.0 && rho_f <= 1e-2 && 0.1 * rho_f > itol;
+      if (loosened) itol = 0.1 * rho_f;
       if (worst > 0) itol = std::min(1e-2, std::max(itol, 0.1 * tol / worst));
+      rprev = rinf;
       if ((rc = papply(h->d_ro, h->d_z))) return rc;
       // columns already converged keep their x
       Coef3 cf{};
@@ -1537,6 +1550,11 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       }
       lincomb(R, n, cf, h->d_xo, h->d_z, nullptr, h->d_xo, s);
       if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
+      double rho = 0.0;
+      for (int j = 0; j < k; ++j)
+        if (rprev[j] > 0 && !conv_col(j, rprev[j])) rho = std::max(rho, rinf[j] / rprev[j]);
+      if (!loosened) rho_f = rho;
+      else if (rho > 10.0 * rho_f) loosen_off = true;
       outer += 1;
     }
   } else {

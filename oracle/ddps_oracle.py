@@ -340,11 +340,17 @@ class Preconditioner:
         return self._Ghat
 
     # -- Figure 2 ------------------------------------------------------------
-    def apply(self, y, reduced="dense", inner_tol=1e-12, inner_maxit=1000, zhat0=None, inner_prec=None):
+    def apply(self, y, reduced="dense", inner_tol=1e-12, inner_maxit=1000, zhat0=None, inner_prec=None,
+              retrieval="spikes"):
         """Solve P z = y.  Returns z, and a dict with g, g^, z^ and the inner
         iteration record.  inner_prec="local" preconditions the inner
         BiCGStab with z -> z - N z (N = local_matvec), the first term of the
-        Neumann series of the interface-local blocks of G^."""
+        Neumann series of the interface-local blocks of G^.
+
+        retrieval="spikes" is step 6.5 as printed, z = g - G z with z(c) = z^.
+        retrieval="resolve" is the same result written without the spikes:
+        since G = D~^{-1} R~, g - G z = D~^{-1}(y - R~ z), one more block solve
+        against y - R~ z (R~ has columns only in c, where z = z^)."""
         y = np.asarray(y, dtype=np.float64)
         g = np.empty(self.n)
         for b, fac in zip(self.blocks, self.factors):                         # 6.1
@@ -359,7 +365,17 @@ class Preconditioner:
             M = (lambda v: v - self.local_matvec(v)) if inner_prec == "local" else None
             zh, inner = bicgstab(self.ghat_matvec, gh, x0=zhat0, tol=inner_tol,
                                  maxit=inner_maxit, precond=M)
-        z = g - self.g_times(zh)                                              # 6.4, 6.5
+        if retrieval == "spikes":
+            z = g - self.g_times(zh)                                          # 6.4, 6.5
+        elif retrieval == "resolve":
+            zfull = np.zeros(self.n)                                          # 6.4
+            zfull[self.c] = zh
+            z = np.empty(self.n)
+            for b, fac, ci in zip(self.blocks, self.factors, self.c_i):       # 6.5, re-solved
+                rhs = y[b.lo:b.hi] - (b.Ri[:, ci] @ zfull[ci] if ci.size else 0.0)
+                z[b.lo:b.hi] = block_solve(fac, rhs)
+        else:
+            raise ValueError(retrieval)
         return z, dict(g=g, ghat=gh, zhat=zh, inner=inner)
 
 
@@ -377,16 +393,20 @@ class SolveInfo:
 
 
 def solve(n, row_ptr, col, val, part_ptr, f, delta=0.0, tol=1e-10, outer="refine",
-          outer_maxit=1000, reduced="dense", inner_tol=1e-12, inner_maxit=1000, prec=None):
-    """DDPS for Ax = f.  outer in {'none', 'refine', 'bicgstab'}."""
+          outer_maxit=1000, reduced="dense", inner_tol=1e-12, inner_maxit=1000, prec=None,
+          retrieval="spikes", norm="inf"):
+    """DDPS for Ax = f.  outer in {'none', 'refine', 'bicgstab'}; the outer
+    stopping test is ||f - Ax|| / ||f|| <= tol in the norm `norm` ('inf',
+    the paper's choice in Section 4, or '2')."""
     P = prec if prec is not None else Preconditioner(n, row_ptr, col, val, part_ptr, delta)
     A = P.A
     f = np.asarray(f, dtype=np.float64)
     info = SolveInfo()
-    fn = np.linalg.norm(f, np.inf)
+    nrm = (lambda v: np.linalg.norm(v, np.inf)) if norm == "inf" else (lambda v: np.linalg.norm(v))
+    fn = nrm(f)
 
     def papply(y):
-        z, d = P.apply(y, reduced=reduced, inner_tol=inner_tol, inner_maxit=inner_maxit)
+        z, d = P.apply(y, reduced=reduced, inner_tol=inner_tol, inner_maxit=inner_maxit, retrieval=retrieval)
         info.applications += 1
         info.inner_iters_total += d["inner"].iters
         return z
@@ -396,32 +416,37 @@ def solve(n, row_ptr, col, val, part_ptr, f, delta=0.0, tol=1e-10, outer="refine
     elif outer == "refine":
         x = np.zeros(n)
         r = f.copy()
-        while np.linalg.norm(r, np.inf) > tol * fn and info.outer_iters < outer_maxit:
+        while nrm(r) > tol * fn and info.outer_iters < outer_maxit:
             x = x + papply(r)
             r = f - A @ x
             info.outer_iters += 1
     elif outer == "bicgstab":
-        x, kinfo = bicgstab(lambda v: A @ v, f, tol=tol, maxit=outer_maxit, precond=papply,
-                            norm=lambda v: np.linalg.norm(v, np.inf))
+        x, kinfo = bicgstab(lambda v: A @ v, f, tol=tol, maxit=outer_maxit, precond=papply, norm=nrm)
         info.outer_iters = kinfo.iters
     else:
         raise ValueError(outer)
     r = f - A @ x
-    info.relres_inf = float(np.linalg.norm(r, np.inf) / fn) if fn else 0.0
-    info.relres_2 = float(np.linalg.norm(r) / np.linalg.norm(f)) if fn else 0.0
-    info.converged = info.relres_inf <= tol
+    finf, f2 = np.linalg.norm(f, np.inf), np.linalg.norm(f)
+    info.relres_inf = float(np.linalg.norm(r, np.inf) / finf) if finf else 0.0
+    info.relres_2 = float(np.linalg.norm(r) / f2) if f2 else 0.0
+    info.converged = (info.relres_inf if norm == "inf" else info.relres_2) <= tol
     return x, info, P
 
 
-def hager_higham_cond1(A_dense_solve, A_dense_solveT, n, A1norm, iters=5):
-    """1-norm condition estimate (Hager 1984, Higham 1988) from solve callbacks."""
+def hager_higham_cond1(solve, solveT, n, A1norm, iters=5):
+    """Estimate of kappa_1(A) = ||A||_1 ||A^{-1}||_1 (Hager 1984; Higham 1988,
+    Algorithm 2.1): a power-method style search for the column of A^{-1}
+    with the largest 1-norm, from solves with A and A^T.  The estimate of
+    ||A^{-1}||_1 is ||A^{-1} x||_1 for a unit-1-norm x, so it never exceeds
+    the true value; it is usually exact or within a small factor.
+    solve(v) = A^{-1} v, solveT(v) = A^{-T} v; A1norm = ||A||_1."""
     x = np.full(n, 1.0 / n)
     est = 0.0
     for _ in range(iters):
-        y = A_dense_solve(x)
+        y = solve(x)
         est_new = np.linalg.norm(y, 1)
         xi = np.sign(y); xi[xi == 0] = 1.0
-        z = A_dense_solveT(xi)
+        z = solveT(xi)
         j = int(np.argmax(np.abs(z)))
         if est_new <= est or np.abs(z[j]) <= z @ x:
             est = max(est, est_new)
@@ -429,3 +454,48 @@ def hager_higham_cond1(A_dense_solve, A_dense_solveT, n, A1norm, iters=5):
         est = est_new
         x = np.zeros(n); x[j] = 1.0
     return est * A1norm
+
+
+def cond1_dense_estimate(A):
+    """kappa_1 estimate of a (small) matrix through its dense LU: the
+    Hager-Higham search above with LAPACK solves."""
+    import scipy.linalg as sla
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    lu = sla.lu_factor(Ad)
+    n = Ad.shape[0]
+    return hager_higham_cond1(lambda v: sla.lu_solve(lu, v), lambda v: sla.lu_solve(lu, v, trans=1), n,
+                              np.linalg.norm(Ad, 1))
+
+
+def mmatrix_kinf_bounds(A, y):
+    """Two-sided bounds on kappa_inf(A) = ||A||_inf ||A^{-1}||_inf from any
+    vector y > 0 (for example an approximate solution of A y = 1).
+
+    For a Z-matrix A (off-diagonal entries <= 0), a vector y > 0 with A y > 0
+    proves that A is a nonsingular M-matrix, so that A^{-1} >= 0 entrywise
+    and ||A^{-1}||_inf = ||A^{-1} 1||_inf (Berman & Plemmons, Ch. 6).  With
+    r = A y:  A^{-1} 1 <= y / min(r) gives the upper bound, and
+    y = A^{-1} r gives ||A^{-1}||_inf >= ||y||_inf / ||r||_inf.  r is formed
+    in float64 and widened by a bound on its rounding error
+    (|fl(Ay) - Ay| <= gamma_k |A| |y|, k the longest row), so the bounds hold
+    whatever y is.  Returns (lo, hi), or None if A is not a Z-matrix or the
+    certificate fails (some entry of y or of A y not positive)."""
+    A = sp.csr_matrix(A)
+    y = np.asarray(y, dtype=np.float64)
+    coo = A.tocoo()
+    off = coo.row != coo.col
+    if np.any(coo.data[off] > 0.0) or not np.all(y > 0.0):
+        return None
+    r = A @ y
+    kmax = int(np.max(np.diff(A.indptr))) if A.nnz else 1
+    u = np.finfo(np.float64).eps / 2
+    gam = kmax * u / (1.0 - kmax * u)
+    err = gam * (abs(A) @ np.abs(y))
+    rmin = float(np.min(r - err))
+    if not rmin > 0.0:
+        return None
+    ainf = float(np.max(abs(A) @ np.ones(A.shape[0])))
+    ynorm = float(np.max(y))
+    hi = ainf * ynorm / rmin
+    lo = ainf * ynorm / float(np.max(np.abs(r) + err))
+    return lo, hi

@@ -16,13 +16,18 @@ addition beside the method (its residual decides whether its guess is used).
   loss = mean((y - target)^2)  over all batch x d_out entries
 
 Backward pass: the chain rule written out layer by layer; Adam: Kingma & Ba
-(2015), Algorithm 1, with bias correction.  All arithmetic is float64; the
-`bf16` switch rounds the tensors the GPU keeps in bfloat16 (weights used in
-the products, the input, the stored activations and, in the backward pass,
-the output error dy and the pre-activation errors dz) to bfloat16 with
-round-to-nearest-even at the same points, so the two sides differ only by
-accumulation order and by where the ReLU test falls for z within rounding
-of zero.
+(2015), Algorithm 1, with bias correction.  All arithmetic is float64.
+
+The `bf16` switch follows the network's stated precision, "bf16 weights and
+activations, FP32 accumulation", read as: every operand of a product is a
+bfloat16 value and every sum is an accumulator.  So the weights as used, the
+input, the stored activations of the forward pass, and the activations of the
+backward pass (the output error dy and the pre-activation errors dz, which
+are the operands of the backward products) are rounded to bfloat16 (nearest,
+ties to even); sums, biases, the output y and the parameter gradients (FP32
+master parameters) are not.  The element-by-element form of this reading is
+pinned in the tests.  Two implementations of it differ only by accumulation
+order and by where the ReLU test falls for z within rounding of zero.
 """
 from __future__ import annotations
 

@@ -139,3 +139,74 @@ def test_guess_features_compose_target_round_trip():
     z0 = M.guess_compose(zp, T, s, mask, t)
     assert np.allclose(z0, zh, rtol=1e-6, atol=1e-6 * np.max(np.abs(zh)))
     assert np.all(z0[mask == 0] == 0)
+
+
+def _bf16_scalar(v):
+    """Nearest bfloat16 of a float (ties to even), via the float32 bit
+    pattern: bfloat16 is the top 16 bits of a float32."""
+    import struct
+    bits = struct.unpack("<I", struct.pack("<f", float(v)))[0]
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return struct.unpack("<f", struct.pack("<I", bits))[0]
+
+
+def _loop_net(params, x, t):
+    """The network's bf16 mode written out element by element.  Rounding
+    points, read from 'bf16 weights and activations, FP32 accumulation': the
+    operands of every product are bf16 (weights as used, the input, the
+    stored activations, and in the backward pass the activation gradients dy
+    and dz that the backward products consume); sums, biases, the output y
+    and the parameter gradients are not rounded (FP32 accumulators and FP32
+    master parameters).  Sums are taken in Python floats so that only the
+    rounding points, not the summation order, can differ."""
+    W = [params[0], params[2], params[4], params[6]]
+    bvec = [params[1], params[3], params[5], params[7]]
+    B = len(x)
+    act = [[[_bf16_scalar(v) for v in row] for row in x]]
+    pre = []
+    for l in range(4):
+        a = act[-1]
+        fi, fo = W[l].shape
+        z = [[sum(a[r][i] * _bf16_scalar(W[l][i][j]) for i in range(fi)) + bvec[l][j] for j in range(fo)]
+             for r in range(B)]
+        pre.append(z)
+        if l < 3:
+            act.append([[_bf16_scalar(max(v, 0.0)) for v in row] for row in z])
+    y = pre[3]
+    N = B * len(y[0])
+    dz = [[_bf16_scalar(2.0 * (y[r][j] - t[r][j]) / N) for j in range(len(y[0]))] for r in range(B)]
+    grads = [None] * 8
+    for l in range(3, -1, -1):
+        a = act[l]
+        fi, fo = W[l].shape
+        grads[2 * l] = np.array([[sum(a[r][i] * dz[r][j] for r in range(B)) for j in range(fo)] for i in range(fi)])
+        grads[2 * l + 1] = np.array([sum(dz[r][j] for r in range(B)) for j in range(fo)])
+        if l > 0:
+            zprev = pre[l - 1]
+            dz = [[_bf16_scalar(sum(dz[r][j] * _bf16_scalar(W[l][i][j]) for j in range(fo))
+                                * (1.0 if zprev[r][i] > 0 else 0.0)) for i in range(fi)] for r in range(B)]
+    return np.array(y), grads
+
+
+def test_bf16_mode_matches_elementwise_definition():
+    # Random (non-representable) weights and inputs: every bf16 rounding point
+    # of the vectorised oracle must sit where the element-by-element
+    # definition puts it; a missing or extra rounding moves results by about
+    # 2^-9 relative, far above the 1e-12 allowed here for summation order.
+    rng = np.random.default_rng(21)
+    dims = [5, 4, 4, 4, 3]
+    params = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        params.append(rng.uniform(-1.3, 1.3, (a, b)))
+        params.append(rng.uniform(-0.2, 0.2, b))
+    x = rng.uniform(-2, 2, (3, 5))
+    t = rng.uniform(-1, 1, (3, 3))
+    y_loop, g_loop = _loop_net(params, x, t)
+    y, cache = M.forward(params, x, bf16=True)
+    g = M.backward(params, cache, y, t, bf16=True)
+    assert np.allclose(y, y_loop, rtol=1e-12, atol=1e-12)
+    for a, b in zip(g, g_loop):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
+    # the rounding is not a no-op on these values
+    y64, c64 = M.forward(params, x, bf16=False)
+    assert np.max(np.abs(y64 - y)) > 1e-4

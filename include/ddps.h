@@ -348,6 +348,20 @@ int ddps_mlp_gradients(ddps_mlp m, int32_t batch, const float* X, const float* T
 /* Releases the network; NULL is ignored. */
 void ddps_mlp_destroy(ddps_mlp m);
 
+/* Residual of the outer stopping test (Section 4: ||f - Ax||_inf / ||f||_inf,
+ * Section 3: the relative residual of the outer iteration) for k columns,
+ * without a handle: r = f - A x for the CSR matrix A (device: int64 row_ptr
+ * [n+1], int32 col and double val [nnz]) and X, F (device, column-major n x k
+ * with leading dimensions ldx, ldf >= n).  R (device, may be NULL) receives r
+ * (leading dimension ldr >= n).  norms (host, double[4k]) receives per column
+ * j: ||r||_inf, ||r||_2, ||f||_inf, ||f||_2.  1 <= k <= 8.  Ordered on
+ * `stream` (a hipStream_t, NULL = null stream) and synchronises it.  The
+ * partial sums of the reduction (256 KiB of device memory) are allocated
+ * and freed by the call.  Errors: DDPS_E_ARG, DDPS_E_NOMEM, DDPS_E_HIP. */
+int ddps_residual_norms(int64_t n, int32_t k, const int64_t* row_ptr, const int32_t* col, const double* val,
+                        const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
+                        double* norms, void* stream);
+
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);
 

@@ -2217,6 +2217,34 @@ int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms,
   return DDPS_OK;
 }
 
+int ddps_residual_norms(int64_t n, int32_t k, const int64_t* row_ptr, const int32_t* col, const double* val,
+                        const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
+                        double* norms, void* stream) {
+  if (n <= 0 || k < 1 || k > kMaxRhs || !row_ptr || !col || !val || !X || !F || !norms || ldx < n || ldf < n ||
+      (R && ldr < n))
+    return DDPS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t part_bytes = sizeof(double) * (size_t)kVecGrid * kMaxRhs * 4;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, part_bytes + sizeof(double) * 4 * kMaxRhs) != hipSuccess) return DDPS_E_NOMEM;
+  double* part = (double*)buf;
+  double* out = part + (size_t)kVecGrid * kMaxRhs * 4;
+  residual_norms_cols(n, k, row_ptr, col, val, X, ldx, F, ldf, R, ldr, part, out, s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(norms, out, sizeof(double) * 4 * k, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(buf);
+  if (e != hipSuccess) {
+    last_hip_error() = e;
+    return DDPS_E_HIP;
+  }
+  for (int j = 0; j < k; ++j) {
+    norms[4 * j + 1] = std::sqrt(norms[4 * j + 1]);
+    norms[4 * j + 3] = std::sqrt(norms[4 * j + 3]);
+  }
+  return DDPS_OK;
+}
+
 int ddps_memory(ddps_handle h, size_t* bytes) {
   if (!h || !bytes) return DDPS_E_ARG;
   *bytes = h->bytes;

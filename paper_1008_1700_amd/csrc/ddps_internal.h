@@ -201,6 +201,12 @@ void bicg_restart(int R, int it, int64_t m, const int32_t* flag, const double* r
 void csr_resid(int R, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                const double* x, int64_t ldx, const double* f, int64_t ldf, double* r, int64_t ldr,
                double* part, int W, double* out, hipStream_t s);
+// r = f - A x and per-column norms (max|r|, sum r^2, max|f|, sum f^2) for
+// k <= kMaxRhs columns; part: device, kVecGrid * kMaxRhs * 4 doubles of
+// partial sums; out: device, 4k doubles.
+void residual_norms_cols(int64_t n, int k, const int64_t* row_ptr, const int32_t* col, const double* val,
+                         const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
+                         double* part, double* out, hipStream_t s);
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s);
 void dot2(int R, int64_t n, const double* a0, const double* b0, const double* a1, const double* b1,

@@ -573,6 +573,22 @@ void csr_resid(int R, int64_t n, const int64_t* row_ptr, const int32_t* col, con
   DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_csr_resid<RR>, dim3(W), dim3(256), 0, s, n, row_ptr, col, val, x, ldx, f, ldf, r, ldr, part));
   DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_resid_reduce<RR>, dim3(1), dim3(64), 0, s, W, part, out));
 }
+// Residual norms of k <= 8 columns in column groups of 8, 4, 2 and 1 (the
+// kernels' widths), each group through the same two kernels as the outer
+// layer; part holds [W][8][4] partials, out [k][4] (device).
+void residual_norms_cols(int64_t n, int k, const int64_t* row_ptr, const int32_t* col, const double* val,
+                         const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
+                         double* part, double* out, hipStream_t s) {
+  const int W = (int)grid_for(n);
+  int j0 = 0;
+  while (j0 < k) {
+    const int rest = k - j0;
+    const int g = rest >= 8 ? 8 : rest >= 4 ? 4 : rest >= 2 ? 2 : 1;
+    csr_resid(g, n, row_ptr, col, val, X + (int64_t)j0 * ldx, ldx, F + (int64_t)j0 * ldf, ldf,
+              R ? R + (int64_t)j0 * ldr : nullptr, ldr, part, W, out + 4 * j0, s);
+    j0 += g;
+  }
+}
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s) {
   DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_lincomb<RR>, dim3(grid_for(n)), dim3(256), 0, s, n, cf, X, Y, Z, out));

@@ -112,6 +112,7 @@ _SIGS = {
     "ddps_mlp_gradients": (_I32, [_P, _I32, _P, _P, _P, ctypes.POINTER(_D)]),
     "ddps_mlp_destroy": (None, [_P]),
     "ddps_memory": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "ddps_residual_norms": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D), _P]),
     "ddps_destroy": (None, [_P]),
     "ddps_status_string": (ctypes.c_char_p, [_I32]),
 }
@@ -356,6 +357,18 @@ def ddps_mlp_gradients(m, batch, X, T):
 def ddps_mlp_destroy(m):
     if m:
         lib().ddps_mlp_destroy(m)
+
+
+def ddps_residual_norms(row_ptr, col, val, X, F, R=None, stream=None):
+    """X, F (and R): (k, n) contiguous float64 CUDA tensors (row j = column j).
+    Returns a (k, 4) array: ||r||_inf, ||r||_2, ||f||_inf, ||f||_2."""
+    k, n = F.shape
+    out = np.zeros(4 * k)
+    rc = lib().ddps_residual_norms(int(n), int(k), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(X), int(n), _ptr(F),
+                                   int(n), _ptr(R), int(n), out.ctypes.data_as(ctypes.POINTER(_D)),
+                                   ctypes.c_void_p(stream))
+    _chk(rc, "ddps_residual_norms")
+    return out.reshape(k, 4)
 
 
 def ddps_memory(h):

@@ -362,6 +362,20 @@ int ddps_residual_norms(int64_t n, int32_t k, const int64_t* row_ptr, const int3
                         const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
                         double* norms, void* stream);
 
+/* As ddps_residual_norms, for callers that cannot allocate device memory
+ * (for example code that must not call hipMalloc in a serving loop): the call
+ * allocates nothing.  Its partial sums live in a fixed device array of the
+ * library (262,400 bytes per GPU, held until the process ends); k > 8 is
+ * refused with DDPS_E_ARG since the array holds 8 columns.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other host
+ * threads, or other streams before this call's synchronisation) race; calls
+ * in sequence are safe, since every entry a call reads it first writes.
+ * Same arguments, results and errors as ddps_residual_norms (DDPS_E_HIP also
+ * if the array's device address cannot be found). */
+int ddps_residual_norms_noalloc(int64_t n, int32_t k, const int64_t* row_ptr, const int32_t* col,
+                                const double* val, const double* X, int64_t ldx, const double* F, int64_t ldf,
+                                double* R, int64_t ldr, double* norms, void* stream);
+
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);
 

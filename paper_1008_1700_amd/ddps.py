@@ -113,6 +113,8 @@ _SIGS = {
     "ddps_mlp_destroy": (None, [_P]),
     "ddps_memory": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "ddps_residual_norms": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D), _P]),
+    "ddps_residual_norms_noalloc": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D),
+                                           _P]),
     "ddps_destroy": (None, [_P]),
     "ddps_status_string": (ctypes.c_char_p, [_I32]),
 }

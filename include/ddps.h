@@ -89,6 +89,17 @@ typedef struct {
                               of G(c,c) (entries whose row and column lie at the same block
                               boundary), right-preconditioned; it changes the iterates, not
                               the solved system */
+  int32_t retrieval;       /* step 6.5 of Figure 2: 0 = z = g - G z (z(c) = z^), with the
+                              spikes G kept in full; 1 = the same vector written without the
+                              spikes, z = D~^{-1}(y - R~ z) (G = D~^{-1} R~): one more block
+                              solve per application, and only the spike rows at c (the tips
+                              that form G^) are kept.  The spikes are then computed batch by
+                              batch in a workspace of work_slots blocks, which is what lets
+                              large systems fit */
+  int32_t norm;            /* norm of the outer stopping test ||f - Ax|| / ||f|| <= tol:
+                              0 = inf-norm (Section 4), 2 = 2-norm */
+  int32_t work_slots;      /* retrieval 1: blocks whose spikes are computed at once (0 = as
+                              many as the memory budget allows, at most p) */
 } ddps_options;
 
 typedef struct {
@@ -107,7 +118,8 @@ typedef struct {
 /* Fills *opt with the defaults: delta 0, FP64 factors, inner_tol 1e-12,
  * inner_maxit 1000, outer_maxit 1000, iterative refinement, zero guess,
  * max_rhs 1, no memory budget, null stream, automatic stream groups, no
- * graph, no inner preconditioner. */
+ * graph, no inner preconditioner, spikes kept in full (retrieval 0),
+ * inf-norm stopping test, automatic workspace slots. */
 void ddps_default_options(ddps_options* opt);
 
 /* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row
@@ -115,7 +127,10 @@ void ddps_default_options(ddps_options* opt);
  * build the index set c of kept coupling columns.
  *   n, p:        matrix order and number of blocks (p >= 1).
  *   part_ptr:    host, int64[p+1]; block i owns rows [part_ptr[i], part_ptr[i+1]);
- *                part_ptr[0] = 0, strictly increasing, part_ptr[p] = n.
+ *                part_ptr[0] = 0, strictly increasing, part_ptr[p] = n.  A host
+ *                array because the block layout and the memory plan (and so
+ *                the F1 check) are made on the host before any large
+ *                allocation; the library keeps its own copies.
  *   row_ptr:     device, int64[n+1]; col: device, int32[nnz]; val: device, double[nnz].
  *   opt:         host, may be NULL for the defaults.
  * The library copies what it needs: the caller may free the CSR arrays when
@@ -195,15 +210,19 @@ int ddps_reduced_matvec(ddps_handle h, int32_t k, const double* x, double* v);
  *   which = 0: the diagonal tile k holding inverse factors: strictly below
  *              the diagonal L_kk^{-1} (unit diagonal implied), on and above
  *              it U_kk^{-1};
- *   which = 1: L_{k+1,k}, the sub-diagonal tile of L (k < T-1);
- *   which = 2: U_{k,k+1}, the super-diagonal tile of U (k < T-1).
- * dst: device, double[t*t], column-major. */
+ *   which = 1: L_{k+1,k}, the sub-diagonal tile of L (k < T-1), upper
+ *              triangular (zero below the diagonal);
+ *   which = 2: U_{k,k+1}, the super-diagonal tile of U (k < T-1), lower
+ *              triangular (zero above the diagonal).
+ * The two off-diagonal factors of a tile row share one t x (t+1) array (a
+ * pair of triangles).  dst: device, double[t*t], column-major. */
 int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* dst);
 
 /* Spikes of block blk as double: dst (device, double[n_i * 2t], column-major,
  * leading dimension n_i, padding rows removed); columns [0,t) multiply the
  * last t columns of block blk-1, columns [t,2t) the first t columns of block
- * blk+1 (all zero where that neighbour does not exist). */
+ * blk+1 (all zero where that neighbour does not exist).  DDPS_E_STATE with
+ * retrieval 1 (only the tips are kept). */
 int ddps_get_spikes(ddps_handle h, int32_t blk, double* dst);
 
 /* Tile size t and per-block padded sizes: tiles (host, int32[p]) receives

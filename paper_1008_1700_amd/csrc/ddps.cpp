@@ -86,7 +86,17 @@ struct ddps_ctx {
   size_t elt = 8;
   std::vector<BlockInfo> blk;
   int Tmax = 0;
-  int64_t Np = 0, m = 0, ntiles = 0, nspike = 0, scr_per_block = 0;
+  int64_t Np = 0, m = 0, tile_elems = 0, nspike = 0, scr_per_block = 0;
+  // Tips only (retrieval = 1): the spikes are computed in a workspace of
+  // `nslots` block slots (scratch and an Nmax x 2t spike matrix each), batch
+  // after batch, and only their tips are kept (d_tipcm); the coupling entries
+  // wait in the compact store d_rhs.  wslot[i] is block i's slot in the
+  // current schedules (i itself when every block has its own).
+  bool tips_only = false;
+  int64_t nslots = 0, Nmax = 0;
+  std::vector<int64_t> wslot;
+  void* d_rhs = nullptr;     // p pairs of t x (t+1): left coupling (upper), right coupling (lower)
+  void* d_tipcm = nullptr;   // 2(p-1) tip parts, t x 2t column-major (ld t), part 2i-1 / 2i as in d_tips
   int R = 1;
   // device data
   int64_t *d_part = nullptr, *d_rowptr = nullptr;
@@ -184,18 +194,33 @@ struct ddps_ctx {
   }
 
   // ---- addressing -------------------------------------------------------
-  char* tile(int i, int which, int k) const {  // which: 0 diag, 1 L_{k+1,k}, 2 U_{k,k+1}
+  // Elements of a pair of triangles: a t x (t+1) column-major array holding
+  // a lower triangle (diagonal included) at offset 0 and an upper one at
+  // offset t, both read with leading dimension t.
+  int64_t pair_elems() const { return (int64_t)t * t + t; }
+  // which 0: diagonal tile k; 1: A_{k+1,k} (upper half of pair k); 2:
+  // A_{k,k+1} (lower half of pair k).  Halves are read through masks.
+  char* tile(int i, int which, int k) const {
     const BlockInfo& B = blk[i];
-    const int64_t idx = B.tiles + (which == 0 ? k : which == 1 ? B.T + k : 2 * B.T - 1 + k);
-    return (char*)d_tiles + (size_t)idx * t * t * elt;
+    const int64_t tt = (int64_t)t * t;
+    const int64_t idx = which == 0 ? B.tiles + k * tt
+                                   : B.tiles + B.T * tt + k * pair_elems() + (which == 1 ? t : 0);
+    return (char*)d_tiles + (size_t)idx * elt;
   }
-  // L_{k+1,k} (which 1) or U_{k,k+1} (which 2) of block i
+  // L_{k+1,k} (which 1, upper triangular) or U_{k,k+1} (which 2, lower
+  // triangular) of block i: halves of one pair
   char* lu(int i, int which, int k) const {
     if (!d_lu) return tile(i, which, k);
-    const BlockInfo& B = blk[i];
-    const int64_t idx = lu_off[i] + (which == 1 ? k : B.T - 1 + k);
-    return (char*)d_lu + (size_t)idx * t * t * elt;
+    const int64_t idx = lu_off[i] + k * pair_elems() + (which == 1 ? t : 0);
+    return (char*)d_lu + (size_t)idx * elt;
   }
+  // compact coupling store of block i: which 1 = left coupling C_i (upper),
+  // 2 = right coupling B_i (lower)
+  char* rhs(int i, int which) const {
+    return (char*)d_rhs + (size_t)(i * pair_elems() + (which == 1 ? t : 0)) * elt;
+  }
+  // column-major tip part q (t x 2t, leading dimension t)
+  char* tipcm(int64_t q) const { return (char*)d_tipcm + (size_t)(q * 2 * t * (int64_t)t) * elt; }
   char* sub(char* tile_base, int r, int c) const {  // element (r, c) of a t x t tile
     return tile_base + ((size_t)c * t + r) * elt;
   }
@@ -218,7 +243,7 @@ struct ddps_ctx {
       case 4: off = 4 * tt; break;
       default: off = 4 * tt + half; break;
     }
-    return (char*)d_scratch + (size_t)(i * scr_per_block + off) * elt;
+    return (char*)d_scratch + (size_t)(wslot[i] * scr_per_block + off) * elt;
   }
 
   void tim_begin(int kind, hipEvent_t& a, hipStream_t s) {
@@ -448,13 +473,13 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       const int N = (int)B.N;
       if (k >= 1)
         sb.add_gemm(h->lu(i, 1, k - 1), t, h->lu(i, 2, k - 1), t, h->tile(i, 0, k), t, h->tile(i, 0, k), t,
-                    t, t, t, G_NEG | G_A_UP | G_B_LO);
+                    t, t, t, G_NEG | G_A_UP | G_A_MUP | G_B_LO | G_B_MLO);
       if (i > 0) {
         // the right-hand side of the left spike is nonzero in rows < 2t only
         if (k >= 1)
           sb.add_gemm(h->lu(i, 1, k - 1), t, h->spike(i, (int64_t)(k - 1) * t, 0), N,
                       (int64_t)k * t < 2 * (int64_t)t ? h->spike(i, (int64_t)k * t, 0) : nullptr, N, h->scr(i, 0), t,
-                      t, t, t, G_NEG | G_A_UP);
+                      t, t, t, G_NEG | G_A_UP | G_A_MUP);
         else
           sb.add_copy(h->spike(i, 0, 0), N, h->scr(i, 0), t, t, t);
       }
@@ -574,8 +599,11 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       if (k < B.T - 1) {
         const char* a_lo = h->d_lu ? h->tile(i, 1, k) : h->scr(i, 1);   // A_{k+1,k}
         const char* a_up = h->d_lu ? h->tile(i, 2, k) : h->scr(i, 2);   // A_{k,k+1}
-        sb.add_gemm(a_lo, t, D, t, nullptr, 0, h->lu(i, 1, k), t, t, t, t, G_A_UP | G_B_MUP | G_B_UP);
-        sb.add_gemm(D, t, a_up, t, nullptr, 0, h->lu(i, 2, k), t, t, t, t, G_A_MLU | G_A_LO | G_B_LO);
+        // each product writes its own half of the pair
+        sb.add_gemm(a_lo, t, D, t, nullptr, 0, h->lu(i, 1, k), t, t, t, t,
+                    G_A_UP | G_A_MUP | G_B_MUP | G_B_UP | G_D_UP);
+        sb.add_gemm(D, t, a_up, t, nullptr, 0, h->lu(i, 2, k), t, t, t, t,
+                    G_A_MLU | G_A_LO | G_B_LO | G_B_MLO | G_D_LO);
       }
       if (i > 0) sb.add_gemm(D, t, h->scr(i, 0), t, nullptr, 0, h->spike(i, (int64_t)k * t, 0), N, t, t, t, G_A_MLU | G_A_LO);
       if (k == B.T - 1 && i < p - 1)
@@ -602,10 +630,10 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
           const int cm = std::max(c0, t);
           if (cm > c0)
             sb.add_gemm(h->lu(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, c0), N,
-                        h->spike(i, (int64_t)k * t, c0), N, W, t, t, cm - c0, t, G_NEG | G_A_LO);
+                        h->spike(i, (int64_t)k * t, c0), N, W, t, t, cm - c0, t, G_NEG | G_A_LO | G_A_MLO);
           if (c1 > cm)
             sb.add_gemm(h->lu(i, 2, k), t, h->spike(i, (int64_t)(k + 1) * t, cm), N, nullptr, 0,
-                        h->scr(i, 0) + (size_t)cm * t * h->elt, t, t, c1 - cm, t, G_NEG | G_A_LO);
+                        h->scr(i, 0) + (size_t)cm * t * h->elt, t, t, c1 - cm, t, G_NEG | G_A_LO | G_A_MLO);
         } else {
           sb.add_copy(h->spike(i, (int64_t)k * t, c0), N, W, t, t, c1 - c0);
         }
@@ -623,6 +651,47 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       sb.end(S);
     }
   }
+}
+
+// Tips only: the spike right-hand sides of one batch into its workspace
+// slots.  The regions the factorisation reads as right-hand sides are
+// cleared (rows [0, 2t) of the left-coupling columns, the last t rows of the
+// right-coupling columns), then the left coupling C_i (upper triangular)
+// lands at rows [pad, pad + t) and the right coupling B_i (lower triangular)
+// at the last t rows, each copied through an output mask from its half of
+// the compact store.
+void build_batch_rhs(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<int>& mem, std::vector<Launch>& S) {
+  const int t = h->t, p = h->p;
+  sb.begin(LK_GEMM);
+  for (int i : mem) {
+    const BlockInfo& B = h->blk[i];
+    const int N = (int)B.N;
+    if (i > 0) sb.add_copy(nullptr, 0, h->spike(i, 0, 0), N, 2 * t, t);
+    if (i < p - 1) sb.add_copy(nullptr, 0, h->spike(i, B.N - t, t), N, t, t);
+  }
+  sb.end(S);
+  sb.begin(LK_GEMM);
+  for (int i : mem) {
+    const BlockInfo& B = h->blk[i];
+    const int N = (int)B.N;
+    if (i > 0) sb.add_gemm(nullptr, 0, nullptr, 0, h->rhs(i, 1), t, h->spike(i, B.pad, 0), N, t, t, 0, G_D_UP);
+    if (i < p - 1) sb.add_gemm(nullptr, 0, nullptr, 0, h->rhs(i, 2), t, h->spike(i, B.N - t, t), N, t, t, 0, G_D_LO);
+  }
+  sb.end(S);
+}
+
+// Tips only: after a batch's backward sweep, its spike tips (the first t
+// real rows and the last t rows of every G_i, all 2t columns) are copied to
+// the tip store, which is all the reduced system needs.
+void build_batch_tips(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<int>& mem, std::vector<Launch>& S) {
+  const int t = h->t, p = h->p;
+  sb.begin(LK_GEMM);
+  for (int i : mem) {
+    const BlockInfo& B = h->blk[i];
+    if (i > 0) sb.add_copy(h->spike(i, B.pad, 0), (int)B.N, h->tipcm(2 * i - 1), t, t, 2 * t);
+    if (i < p - 1) sb.add_copy(h->spike(i, B.N - t, 0), (int)B.N, h->tipcm(2 * i), t, t, 2 * t);
+  }
+  sb.end(S);
 }
 
 void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
@@ -646,7 +715,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
       G.ce = k >= 1 ? t : 0;
       G.yin = yp + B.voff + (int64_t)k * t;
       G.yout = vp + B.voff + (int64_t)k * t;
-      G.flags = V_NEG | V_YIN;
+      G.flags = V_NEG | V_YIN | (k >= 1 ? V_A_MUP : 0);   // L_{k,k-1}: upper half of a pair
       G.tri = 2;
       sb.add_gemv(G, eb);
     }
@@ -688,7 +757,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
       G.ce = k < B.T - 1 ? t : 0;
       G.yin = yp + B.voff + (int64_t)k * t;
       G.yout = vp + B.voff + (int64_t)k * t;
-      G.flags = V_NEG | V_YIN;
+      G.flags = V_NEG | V_YIN | (k < B.T - 1 ? V_A_MLO : 0);   // U_{k,k+1}: lower half of a pair
       G.tri = 1;
       sb.add_gemv(G, eb);
     }
@@ -714,9 +783,9 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
     }
     sb.end(h->sch_bwd);
   }
-  // retrieval z = g - G z^ into vpad
+  // retrieval z = g - G z^ into vpad (with the full spikes only)
   sb.begin(LK_GEMV);
-  for (int i = 0; i < p; ++i) {
+  for (int i = 0; i < p && !h->tips_only; ++i) {
     const BlockInfo& B = h->blk[i];
     GemvProb G{};
     G.A = h->spike(i, 0, 0);
@@ -753,6 +822,9 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
           const int64_t q = part == 0 ? 2 * i - 1 : 2 * i;
           G.A = (const char*)h->d_tips + (size_t)q * t * 2 * t * h->elt;
           G.lda = 2 * t;
+        } else if (h->tips_only) {
+          G.A = h->tipcm(part == 0 ? 2 * i - 1 : 2 * i);
+          G.lda = t;
         } else {
           G.A = h->spike(i, part == 0 ? B.pad : B.N - t, 0);
           G.lda = B.N;
@@ -824,27 +896,34 @@ int default_groups(const ddps_ctx* h) { return std::max(1, std::min(4, h->p / 8)
 
 // ---------------------------------------------------------------- phases
 int do_scatter(ddps_ctx* h, hipStream_t s) {
-  const int64_t tcount = h->ntiles * (int64_t)h->t * h->t;
+  const int64_t tcount = h->tile_elems;
   // Spikes: the first factorisation zeroes the whole array (the halves no
   // block uses stay zero for good); later ones only the coupling parts that
   // the scatter fills, since the sweeps write every other entry before it
   // is read.  A fill recorded into a graph under capture has not run yet.
+  // With the tips only, the coupling entries go to the compact store (zeroed
+  // here, since the scatter adds into it) and each batch of the
+  // factorisation places them in its workspace slots.
   const bool whole = !h->spikes_zeroed;
+  const int64_t rcount = h->tips_only ? (int64_t)h->p * h->pair_elems() : 0;
   if (h->sdt == 0) {
     fill_f64((double*)h->d_tiles, tcount, 0.0, s);
     if (whole) fill_f64((double*)h->d_spikes, h->nspike, 0.0, s);
+    fill_f64((double*)h->d_rhs, rcount, 0.0, s);
   } else {
     fill_f32((float*)h->d_tiles, tcount, 0.f, s);
     if (whole) fill_f32((float*)h->d_spikes, h->nspike, 0.f, s);
+    fill_f32((float*)h->d_rhs, rcount, 0.f, s);
   }
-  if (!whole) zero_spike_rhs(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, s);
+  if (!whole && !h->tips_only) zero_spike_rhs(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, s);
   if (!h->capturing) h->spikes_zeroed = true;
   fill_u64(h->d_colnorm, (int64_t)h->p * 2 * h->t, 0ull, s);
   fill_u64(h->d_bad, 1, ~0ull, s);
   fill_f64(h->d_mask, h->m, 0.0, s);
   setup_scatter(h->sdt, h->n, h->p, h->t, h->d_part, h->d_blk, h->d_rowptr, h->d_col, h->d_val, h->d_tiles,
-                h->d_spikes, h->d_colnorm, h->d_flags, s);
-  setup_mask(h->sdt, h->p, h->t, h->opt.drop_delta, h->d_blk, h->d_colnorm, h->d_mask, h->d_spikes, s);
+                h->d_spikes, h->tips_only ? h->d_rhs : nullptr, h->d_colnorm, h->d_flags, s);
+  setup_mask(h->sdt, h->p, h->t, h->opt.drop_delta, h->d_blk, h->d_colnorm, h->d_mask, h->d_spikes,
+             h->tips_only ? h->d_rhs : nullptr, s);
   return DDPS_OK;
 }
 
@@ -898,7 +977,7 @@ int enqueue_factor(ddps_ctx* h) {
 // factor schedules of all groups and the solve schedules, uploaded.
 int build_schedules(ddps_ctx* h) {
   const int p = h->p;
-  const int G = std::max(1, std::min(h->groups, p));
+  const int G = std::max(1, std::min<int>(h->groups, (int)std::min<int64_t>(p, h->nslots)));
   std::vector<int> order(p);
   for (int i = 0; i < p; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->blk[a].T > h->blk[b].T; });
@@ -913,11 +992,41 @@ int build_schedules(ddps_ctx* h) {
   sb.h = h;
   h->mode_cursor = 0;
   h->sch_group.assign(G, {});
-  for (int g = 0; g < G; ++g) {
-    std::vector<int> mem;
-    for (int i = 0; i < p; ++i)
-      if (h->group_of[i] == g) mem.push_back(i);
-    build_factor_schedule(h, sb, mem, h->sch_group[g]);
+  h->wslot.assign(p, 0);
+  if (!h->tips_only) {
+    for (int i = 0; i < p; ++i) h->wslot[i] = i;
+    for (int g = 0; g < G; ++g) {
+      std::vector<int> mem;
+      for (int i = 0; i < p; ++i)
+        if (h->group_of[i] == g) mem.push_back(i);
+      build_factor_schedule(h, sb, mem, h->sch_group[g]);
+    }
+  } else {
+    // Each group owns nslots / G workspace slots and runs its blocks in
+    // batches of that many, longest first (a batch's launches last as long
+    // as its longest block); a slot's scratch and spike matrix are reused by
+    // the next batch of the group, which follows on the group's stream.
+    const int64_t per = h->nslots / G;
+    if (per < 1) return DDPS_E_ARG;
+    const int64_t slot_elems = h->Nmax * 2 * h->t;
+    for (int g = 0; g < G; ++g) {
+      std::vector<int> mem;
+      for (int i : order)
+        if (h->group_of[i] == g) mem.push_back(i);
+      for (size_t b0 = 0; b0 < mem.size(); b0 += (size_t)per) {
+        std::vector<int> batch(mem.begin() + b0, mem.begin() + std::min(mem.size(), b0 + (size_t)per));
+        std::sort(batch.begin(), batch.end());
+        for (size_t j = 0; j < batch.size(); ++j) {
+          const int64_t slot = (int64_t)g * per + (int64_t)j;
+          h->wslot[batch[j]] = slot;
+          h->blk[batch[j]].goff = slot * slot_elems;
+        }
+        build_batch_rhs(h, sb, batch, h->sch_group[g]);
+        build_factor_schedule(h, sb, batch, h->sch_group[g]);
+        build_batch_tips(h, sb, batch, h->sch_group[g]);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(h->d_blk, h->blk.data(), sizeof(BlockInfo) * p, hipMemcpyHostToDevice, h->stream));
   }
   h->sch_fwd.clear();
   h->sch_bwd.clear();
@@ -1059,9 +1168,20 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
     for (int j = 0; j < k; ++j)
       if (st[j] == KS_BREAKDOWN) *breakdown = 1;
   }
-  rc = run_schedule(h, h->sch_retr, R, h->m, h->Np, TK_RETR);
-  if (rc) return rc;
-  vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_vpad, z, ldz, s);
+  if (h->opt.retrieval == 1 && h->m > 0) {
+    // 6.5 re-solved: z = D~^{-1}(y - R~ z^), the block sweeps once more
+    coupling_rhs(h->Np, R, k, h->p, h->t, h->d_blk, h->d_rowptr, h->d_col, h->d_val, y, ldy, h->d_zh, h->m,
+                 h->d_mask, h->d_ypad, s);
+    rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_RETR);
+    if (rc) return rc;
+    rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_RETR);
+    if (rc) return rc;
+    vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_ypad, z, ldz, s);
+  } else {
+    rc = run_schedule(h, h->sch_retr, R, h->m, h->Np, TK_RETR);
+    if (rc) return rc;
+    vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_vpad, z, ldz, s);
+  }
   HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
@@ -1117,8 +1237,8 @@ int dots(ddps_ctx* h, int64_t len, const double* a0, const double* b0, const dou
   return DDPS_OK;
 }
 
-// max |v| per column (host)
-int norm_inf(ddps_ctx* h, const double* v, std::vector<double>& out) {
+// max |v| (two = false) or ||v||_2 (two = true) per column (host)
+int norm_of(ddps_ctx* h, const double* v, bool two, std::vector<double>& out) {
   const int R = h->R;
   const int W = vec_grid(h->n);
   csr_resid(R, h->n, nullptr, nullptr, nullptr, nullptr, h->n, v, h->n, nullptr, h->n, h->d_part_buf, W,
@@ -1127,7 +1247,7 @@ int norm_inf(ddps_ctx* h, const double* v, std::vector<double>& out) {
   HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   out.resize(R);
-  for (int j = 0; j < R; ++j) out[j] = h->h_out[4 * j];
+  for (int j = 0; j < R; ++j) out[j] = two ? std::sqrt(h->h_out[4 * j + 1]) : h->h_out[4 * j];
   return DDPS_OK;
 }
 
@@ -1154,6 +1274,9 @@ void ddps_default_options(ddps_options* o) {
   o->factor_streams = 0;
   o->factor_graph = 0;
   o->inner_prec = 0;
+  o->retrieval = 0;
+  o->norm = 0;
+  o->work_slots = 0;
 }
 
 const char* ddps_status_string(int s) {
@@ -1219,7 +1342,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   const ddps_options& o = h->opt;
   if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
       o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
-      o.inner_prec > 1) {
+      o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1273,6 +1396,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->blk.resize(p);
   int64_t tiles = 0, goff = 0, voff = 0;
   h->Tmax = 0;
+  h->Nmax = 0;
+  const int64_t tt = (int64_t)t * t;
   for (int i = 0; i < p; ++i) {
     BlockInfo& B = h->blk[i];
     B.s = part_ptr[i];
@@ -1283,29 +1408,32 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     B.pad = B.N - B.n;
     if (B.N > std::numeric_limits<int32_t>::max()) return fail(DDPS_E_ARG);
     B.tiles = tiles;
-    tiles += 3 * B.T - 2;
+    tiles += B.T * tt + (B.T - 1) * h->pair_elems();
     B.goff = goff;
     goff += p > 1 ? B.N * 2 * t : 0;
     B.voff = voff;
     voff += B.N;
     h->Tmax = std::max<int>(h->Tmax, (int)B.T);
+    h->Nmax = std::max<int64_t>(h->Nmax, B.N);
   }
-  h->ntiles = tiles;
-  h->nspike = goff;
+  h->tile_elems = tiles;
+  h->tips_only = o.retrieval == 1 && p > 1;
   h->Np = voff;
   h->m = p > 1 ? (int64_t)2 * t * (p - 1) : 0;
   h->scr_per_block = ddps_ctx::scratch_elems(t);
+  h->groups = o.factor_streams > 0 ? o.factor_streams : default_groups(h);
   // memory plan (F1 check before the large allocations)
   const int R = h->R;
   const int64_t m = h->m;
   const int64_t Wmax = std::max<int64_t>({(int64_t)kVecGrid, (int64_t)p * 2 * t / 64 + 1, 1});
   size_t need = 0;
-  need += (size_t)h->ntiles * t * t * h->elt;
-  need += (size_t)h->nspike * h->elt;
-  // packed tips (2(p-1) parts of t x 2t = m x 2t) for one or two right-hand sides
-  h->tip_nseg = (R <= 2 && p > 1) ? tipmv_segments(h->sdt, t) : 0;
-  if (h->tip_nseg > 0) need += (size_t)m * 2 * t * h->elt;
-  need += (size_t)p * h->scr_per_block * h->elt;
+  need += (size_t)h->tile_elems * h->elt;
+  // packed tips (2(p-1) parts of t x 2t = m x 2t) for one or two right-hand
+  // sides, or the column-major tips that are all the tips-only form keeps,
+  // and that form's compact store of the coupling entries
+  h->tip_nseg = (R <= 2 && p > 1 && !h->tips_only) ? tipmv_segments(h->sdt, t) : 0;
+  if (h->tip_nseg > 0 || h->tips_only) need += (size_t)m * 2 * t * h->elt;
+  if (h->tips_only) need += (size_t)p * h->pair_elems() * h->elt;
   need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
   need += (size_t)h->Np * R * 8 * 2 + (size_t)h->Np * 8;
   need += (size_t)m * R * 8 * 11;
@@ -1317,21 +1445,40 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(DDPS_E_HIP);
     budget = fr > ((size_t)1 << 30) ? fr - ((size_t)1 << 30) : fr;
   }
-  if (need > budget) return fail(DDPS_E_NOMEM);
+  // workspace: a scratch area per block, and the whole spike array; with the
+  // tips only, `nslots` slots of scratch + an Nmax x 2t spike matrix, as many
+  // as the budget allows (at most p, or opt.work_slots)
+  const size_t slot_bytes = (size_t)(h->scr_per_block + (p > 1 ? h->Nmax * 2 * t : 0)) * h->elt;
+  if (!h->tips_only) {
+    h->nslots = p;
+    h->nspike = goff;
+    need += (size_t)h->nspike * h->elt + (size_t)p * h->scr_per_block * h->elt;
+    if (need > budget) return fail(DDPS_E_NOMEM);
+  } else {
+    if (need >= budget) return fail(DDPS_E_NOMEM);
+    int64_t fit = (int64_t)((budget - need) / slot_bytes);
+    fit = std::min<int64_t>(fit, p);
+    if (o.work_slots > 0) fit = std::min<int64_t>(fit, o.work_slots);
+    if (fit < 1) return fail(DDPS_E_NOMEM);
+    h->nslots = fit;
+    h->groups = (int)std::min<int64_t>(h->groups, fit);
+    h->nspike = fit * h->Nmax * 2 * t;
+    need += (size_t)fit * slot_bytes;
+  }
   int64_t nlu = 0;
   h->lu_off.assign(p, 0);
   for (int i = 0; i < p; ++i) {
     h->lu_off[i] = nlu;
-    nlu += 2 * (h->blk[i].T - 1);
+    nlu += (h->blk[i].T - 1) * h->pair_elems();
   }
-  const size_t lu_bytes = (size_t)nlu * t * t * h->elt;
+  const size_t lu_bytes = (size_t)nlu * h->elt;
   const bool sep_lu = nlu > 0 && need + lu_bytes <= budget;
   void* vp;
   if (sep_lu) {
     if ((rc = h->alloc_raw(vp, lu_bytes))) return fail(rc);
     h->d_lu = vp;
   }
-  if ((rc = h->alloc_raw(vp, (size_t)h->ntiles * t * t * h->elt))) return fail(rc);
+  if ((rc = h->alloc_raw(vp, (size_t)h->tile_elems * h->elt))) return fail(rc);
   h->d_tiles = vp;
   if ((rc = h->alloc_raw(vp, (size_t)std::max<int64_t>(h->nspike, 1) * h->elt))) return fail(rc);
   h->d_spikes = vp;
@@ -1340,7 +1487,13 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
     h->d_tips = vp;
   }
-  if ((rc = h->alloc_raw(vp, (size_t)p * h->scr_per_block * h->elt))) return fail(rc);
+  if (h->tips_only) {
+    if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
+    h->d_tipcm = vp;
+    if ((rc = h->alloc_raw(vp, (size_t)p * h->pair_elems() * h->elt))) return fail(rc);
+    h->d_rhs = vp;
+  }
+  if ((rc = h->alloc_raw(vp, (size_t)h->nslots * h->scr_per_block * h->elt))) return fail(rc);
   h->d_scratch = vp;
   if ((rc = h->alloc(h->d_colnorm, (int64_t)p * 2 * t)) || (rc = h->alloc(h->d_mask, std::max<int64_t>(m, 1))) ||
       (rc = h->alloc(h->d_c, std::max<int64_t>(m, 1))) || (rc = h->alloc(h->d_rrow, std::max<int64_t>(m, 1))) ||
@@ -1395,7 +1548,6 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
       hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess)
     return fail(DDPS_E_HIP);
-  h->groups = o.factor_streams > 0 ? o.factor_streams : default_groups(h);
   h->use_graph = o.factor_graph != 0;
   if ((rc = build_schedules(h))) return fail(rc);
   hipEventRecord(h->ev1, s);
@@ -1493,7 +1645,11 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   std::vector<double> rinf, r2, finf, f2;
   int rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2);
   if (rc) return rc;
-  std::vector<double> fnorm(finf.begin(), finf.end()), f2n(f2.begin(), f2.end());
+  // the stopping norm: inf (Section 4) or 2 (opt.norm); `cur` picks the
+  // residual norms of the chosen kind after each resid()
+  const bool two = h->opt.norm == 2;
+  std::vector<double> fnorm(two ? f2 : finf), f2n(f2.begin(), f2.end()), finfn(finf.begin(), finf.end());
+  auto cur = [&]() -> const std::vector<double>& { return two ? r2 : rinf; };
   auto conv_col = [&](int j, double ri) { return ri <= tol * fnorm[j] || fnorm[j] == 0.0; };
   double outer = 0;
   int64_t inner_total = 0;
@@ -1532,27 +1688,27 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
     double rho_f = -1.0;
     bool loosen_off = false;
     std::vector<double> rprev;
-    while (!all_conv(rinf) && outer < h->opt.outer_maxit) {
+    while (!all_conv(cur()) && outer < h->opt.outer_maxit) {
       double worst = 0.0;   // largest ||r||/||f|| still above the tolerance
       for (int j = 0; j < k; ++j)
-        if (fnorm[j] > 0) worst = std::max(worst, rinf[j] / fnorm[j]);
+        if (fnorm[j] > 0) worst = std::max(worst, cur()[j] / fnorm[j]);
       itol = h->opt.inner_tol;
       const bool loosened = !loosen_off && rho_f > 0.0 && rho_f <= 1e-2 && 0.1 * rho_f > itol;
       if (loosened) itol = 0.1 * rho_f;
       if (worst > 0) itol = std::min(1e-2, std::max(itol, 0.1 * tol / worst));
-      rprev = rinf;
+      rprev = cur();
       if ((rc = papply(h->d_ro, h->d_z))) return rc;
       // columns already converged keep their x
       Coef3 cf{};
       for (int j = 0; j < R; ++j) {
         cf.a[j] = 1.0;
-        cf.b[j] = (j < k && !conv_col(j, rinf[j])) ? 1.0 : 0.0;
+        cf.b[j] = (j < k && !conv_col(j, cur()[j])) ? 1.0 : 0.0;
       }
       lincomb(R, n, cf, h->d_xo, h->d_z, nullptr, h->d_xo, s);
       if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
       double rho = 0.0;
       for (int j = 0; j < k; ++j)
-        if (rprev[j] > 0 && !conv_col(j, rprev[j])) rho = std::max(rho, rinf[j] / rprev[j]);
+        if (rprev[j] > 0 && !conv_col(j, rprev[j])) rho = std::max(rho, cur()[j] / rprev[j]);
       if (!loosened) rho_f = rho;
       else if (rho > 10.0 * rho_f) loosen_off = true;
       outer += 1;
@@ -1562,7 +1718,7 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
     // each half step on the inf-norm relative residual; per-column scalars
     std::vector<double> rho(R, 1.0), rho_old(R, 1.0), alpha(R, 0.0), omega(R, 1.0), d0, d1, nrm;
     std::vector<int> active(R, 0);
-    for (int j = 0; j < k; ++j) active[j] = conv_col(j, rinf[j]) ? 0 : 1;
+    for (int j = 0; j < k; ++j) active[j] = conv_col(j, cur()[j]) ? 0 : 1;
     HIPCHK(hipMemcpyAsync(h->d_rto, h->d_ro, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
     int restarts = 0;
     bool fresh = true;
@@ -1596,7 +1752,7 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       // x += alpha p^ and stops after this half step
       for (int j = 0; j < R; ++j) { cf.a[j] = 1.0; cf.b[j] = -alpha[j]; cf.c[j] = 0.0; }
       lincomb(R, n, cf, h->d_ro, h->d_vo, nullptr, h->d_sh, s);
-      if ((rc = norm_inf(h, h->d_sh, nrm))) return rc;
+      if ((rc = norm_of(h, h->d_sh, two, nrm))) return rc;
       std::vector<int> half(R, 0);
       bool anyh = false, anyfull = false;
       for (int j = 0; j < k; ++j)
@@ -1625,7 +1781,7 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
         cf.a[j] = a ? 1.0 : 0.0; cf.b[j] = a ? -omega[j] : 0.0; cf.c[j] = a ? 0.0 : 1.0;
       }
       lincomb(R, n, cf, h->d_sh, h->d_to, h->d_ro, h->d_ro, s);
-      if ((rc = norm_inf(h, h->d_ro, nrm))) return rc;
+      if ((rc = norm_of(h, h->d_ro, two, nrm))) return rc;
       for (int j = 0; j < k; ++j) {
         if (!active[j]) continue;
         outer = std::max(outer, (double)it);
@@ -1653,11 +1809,11 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   double worst_inf = 0, worst_2 = 0;
   bool ok = true;
   for (int j = 0; j < k; ++j) {
-    const double ri = fnorm[j] > 0 ? rinf[j] / fnorm[j] : 0.0;
+    const double ri = finfn[j] > 0 ? rinf[j] / finfn[j] : 0.0;
     const double rt = f2n[j] > 0 ? r2[j] / f2n[j] : 0.0;
     worst_inf = std::max(worst_inf, ri);
     worst_2 = std::max(worst_2, rt);
-    if (!(ri <= tol)) ok = false;
+    if (!((two ? rt : ri) <= tol)) ok = false;
   }
   if (h->opt.outer_method == 1 && outer == 0 && ok) outer = 0;
   if (info) {
@@ -1868,24 +2024,33 @@ int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* 
   if (!h || !dst || blk < 0 || blk >= h->p || which < 0 || which > 2) return DDPS_E_ARG;
   const BlockInfo& B = h->blk[blk];
   if (k < 0 || k >= B.T || (which > 0 && k >= B.T - 1)) return DDPS_E_ARG;
-  const int64_t tt = (int64_t)h->t * h->t;
+  const int t = h->t;
+  const int64_t tt = (int64_t)t * t;
   const char* src = which == 0 ? h->tile(blk, 0, k) : h->lu(blk, which, k);
+  std::vector<double> out(tt);
   if (h->sdt == 0) {
-    HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * tt, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(out.data(), src, sizeof(double) * tt, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
   } else {
     std::vector<float> tmp(tt);
-    std::vector<double> tmp2(tt);
     HIPCHK(hipMemcpyAsync(tmp.data(), src, sizeof(float) * tt, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    for (int64_t q = 0; q < tt; ++q) tmp2[q] = tmp[q];
-    HIPCHK(hipMemcpyAsync(dst, tmp2.data(), sizeof(double) * tt, hipMemcpyHostToDevice, h->stream));
+    for (int64_t q = 0; q < tt; ++q) out[q] = tmp[q];
   }
+  // the off-diagonal factors are halves of a pair: the other half holds the
+  // other factor, so it is zeroed here (L_{k+1,k} is upper, U_{k,k+1} lower)
+  if (which > 0)
+    for (int64_t c = 0; c < t; ++c)
+      for (int64_t r = 0; r < t; ++r)
+        if (which == 1 ? r > c : r < c) out[c * t + r] = 0.0;
+  HIPCHK(hipMemcpyAsync(dst, out.data(), sizeof(double) * tt, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DDPS_OK;
 }
 
 int ddps_get_spikes(ddps_handle h, int32_t blk, double* dst) {
   if (!h || !dst || blk < 0 || blk >= h->p) return DDPS_E_ARG;
+  if (h->tips_only) return DDPS_E_STATE;   // only the tips are kept
   const BlockInfo& B = h->blk[blk];
   const int t = h->t;
   if (h->p == 1) {

@@ -30,6 +30,10 @@ enum GemmFlag : int32_t {
   G_A_MUP = 128,  // A read as upper: entries on/above the diagonal, 0 below
   G_B_MLU = 256,
   G_B_MUP = 512,
+  G_A_MLO = 1024, // A read as lower: entries on/below the diagonal, 0 above
+  G_B_MLO = 2048,
+  G_D_UP = 4096,  // store only the entries of D on/above the diagonal
+  G_D_LO = 8192,  // store only the entries of D on/below the diagonal
 };
 
 struct GemmProb {
@@ -67,6 +71,7 @@ enum GemvFlag : int32_t {
   V_MASK = 16,    // the product is multiplied row-wise by mask[] before accumulation
   V_DOT = 32,     // emit per-workgroup partials [wg][R][2] of dot(dotv, y_out) (reduced space)
   V_DOT2 = 64,    // ... and of dot(y_out, y_out) in the second slot
+  V_A_MLO = 128,  // A read as lower (masked), diagonal included
 };
 
 struct GemvProb {
@@ -90,11 +95,13 @@ struct GemvProb {
 // ---------------------------------------------------------------- layout
 // Block i owns global rows [s, s+n).  It is padded on top with `pad` identity
 // rows to N = T t rows; padded row pad + j is global row s + j.  Its tiles
-// start at tile index `tiles` of the tile array: A_kk (later the inverse
-// factors) at tiles + k, L_{k+1,k} at tiles + T + k, U_{k,k+1} at
-// tiles + 2T - 1 + k.  Its spike matrix (N x 2t, leading dimension N) starts
-// at element `goff` of the spike array; padded vectors of block i start at
-// `voff`.
+// start at element `tiles` of the tile array: the T diagonal tiles A_kk
+// (later the inverse factors), t x t each, then T-1 pairs of t x (t+1)
+// elements, pair k holding A_{k,k+1} (lower triangular) at offset 0 and
+// A_{k+1,k} (upper triangular) at offset t, both with leading dimension t.
+// Its spike matrix (N x 2t, leading dimension N) starts at element `goff` of
+// the spike array (of its workspace slot when only the tips are kept);
+// padded vectors of block i start at `voff`.
 struct BlockInfo {
   int64_t s, n, pad, N, T;
   int64_t tiles;
@@ -154,11 +161,14 @@ void pack_tips(int dtype, int p, int t, const BlockInfo* blocks, const void* spi
 
 void setup_scan(int64_t n, int p, const int64_t* part, const int64_t* row_ptr, const int32_t* col,
                 const double* val, int64_t nnz, unsigned long long* band, unsigned int* flags, hipStream_t s);
+// rhs: null (coupling entries into the spike array) or the compact store of
+// one t x (t+1) pair per block (left coupling in the upper half, right
+// coupling in the lower half)
 void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, const BlockInfo* blocks,
                    const int64_t* row_ptr, const int32_t* col, const double* val, void* tiles,
-                   void* spikes, unsigned long long* colnorm, unsigned int* flags, hipStream_t s);
+                   void* spikes, void* rhs, unsigned long long* colnorm, unsigned int* flags, hipStream_t s);
 void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
-                const unsigned long long* colnorm, double* mask, void* spikes, hipStream_t s);
+                const unsigned long long* colnorm, double* mask, void* spikes, void* rhs, hipStream_t s);
 // Pivot thresholds per row of the padded layout (Np entries): 1e3 eps times the
 // row's largest in-block magnitude; 0 on padding rows.
 void setup_row_thresh(int64_t n, int p, int64_t Np, const int64_t* part, const BlockInfo* blocks,
@@ -207,6 +217,12 @@ void csr_resid(int R, int64_t n, const int64_t* row_ptr, const int32_t* col, con
 void residual_norms_cols(int64_t n, int k, const int64_t* row_ptr, const int32_t* col, const double* val,
                          const double* X, int64_t ldx, const double* F, int64_t ldf, double* R, int64_t ldr,
                          double* part, double* out, hipStream_t s);
+// yp = y - R~ z^ (padded layout, R columns, k from y, the rest zero): the
+// right-hand side of the re-solved retrieval; zh in the candidate layout
+// (m entries per column), masked to c
+void coupling_rhs(int64_t Np, int R, int k, int p, int t, const BlockInfo* blocks, const int64_t* row_ptr,
+                  const int32_t* col, const double* val, const double* y, int64_t ldy, const double* zh, int64_t m,
+                  const double* mask, double* yp, hipStream_t s);
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s);
 void dot2(int R, int64_t n, const double* a0, const double* b0, const double* a1, const double* b1,

@@ -55,13 +55,25 @@ __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int
   return lo;
 }
 
-// Value of op(X)(r, c) given the stored value v: masks of the packed inverse
-// tiles and zero outside the problem (rows >= rmax or columns >= cmax).
+// Value of op(X)(r, c) given the stored value v: masks of the packed
+// triangles (unit lower, upper, lower with its diagonal) and zero outside the
+// problem (rows >= rmax or columns >= cmax).  A select, so whatever the other
+// triangle of a packed tile holds never reaches a product.
 template <typename T>
-__device__ __forceinline__ T select_op(T v, int r, int c, bool lu, bool up, int rmax, int cmax) {
+__device__ __forceinline__ T select_op(T v, int r, int c, bool lu, bool up, bool lo, int rmax, int cmax) {
   if (lu) v = r > c ? v : (r == c ? T(1) : T(0));
   if (up) v = r <= c ? v : T(0);
+  if (lo) v = r >= c ? v : T(0);
   return (r < rmax && c < cmax) ? v : T(0);
+}
+
+// Output mask of the epilogue: G_D_UP stores only entries on or above the
+// diagonal, G_D_LO only entries on or below it (the two halves of a packed
+// pair of triangles); the other half of the destination is left untouched.
+__device__ __forceinline__ bool store_ok(int fl, int r, int c) {
+  if ((fl & G_D_UP) && r > c) return false;
+  if ((fl & G_D_LO) && r < c) return false;
+  return true;
 }
 
 template <typename T> struct Mma;
@@ -126,6 +138,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
   gptr<T> A = (gptr<T>)P.A;
   gptr<T> B = (gptr<T>)P.B;
   const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_lo = fl & G_A_MLO, b_lo = fl & G_B_MLO;
 
   acc_t acc[MB][NB];
 #pragma unroll
@@ -146,11 +159,11 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
       const int c = k0 + ak + ASTEP * i;
-      ra[i] = select_op(A[(int64_t)c * P.lda + arow], I0 + am, c, a_lu, a_up, P.M, 1 << 30);
+      ra[i] = select_op(A[(int64_t)c * P.lda + arow], I0 + am, c, a_lu, a_up, a_lo, P.M, 1 << 30);
     }
     gptr<T> bp = B + (int64_t)bcol * P.ldb + k0 + bk0;
 #pragma unroll
-    for (int i = 0; i < BE; ++i) rb[i] = select_op(bp[i], k0 + bk0 + i, J0 + bn, b_lu, b_up, 1 << 30, P.N);
+    for (int i = 0; i < BE; ++i) rb[i] = select_op(bp[i], k0 + bk0 + i, J0 + bn, b_lu, b_up, b_lo, 1 << 30, P.N);
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
   gmut<T> D = (gmut<T>)P.D;
   const bool has_c0 = fl & G_C0;
   const T sg = (fl & G_NEG) ? T(-1) : T(1);
-  if (I0 + BM <= P.M && J0 + BN <= P.N) {
+  if (I0 + BM <= P.M && J0 + BN <= P.N && !(fl & (G_D_UP | G_D_LO))) {
 #pragma unroll
     for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_std(const GemmProb* __restric
       for (int v = 0; v < 4; ++v) {
         const int r = I0 + wm * (BM / 2) + mi * 16 + (lane & 15);
         const int c = J0 + wn * (BN / 2) + ni * 16 + Mma<T>::row(lane, v);
-        if (r < P.M && c < P.N) {
+        if (r < P.M && c < P.N && store_ok(fl, r, c)) {
           T val = sg * acc[mi][ni][v];
           if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
           D[(int64_t)c * P.ldd + r] = val;
@@ -253,7 +266,7 @@ __device__ __forceinline__ void store_tile32(const GemmProb& P, const f32x16 (&a
   gmut<float> D = (gmut<float>)P.D;
   const bool has_c0 = P.flags & G_C0;
   const float sg = (P.flags & G_NEG) ? -1.f : 1.f;
-  if (full) {
+  if (full && !(P.flags & (G_D_UP | G_D_LO))) {
 #pragma unroll
     for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
@@ -281,7 +294,7 @@ __device__ __forceinline__ void store_tile32(const GemmProb& P, const f32x16 (&a
       for (int v = 0; v < 16; ++v) {
         const int r = r0 + mi * 32 + (lane & 31);
         const int c = c0 + ni * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        if (r < P.M && c < P.N) {
+        if (r < P.M && c < P.N && store_ok(P.flags, r, c)) {
           float val = sg * acc[mi][ni][v];
           if (has_c0) val += C0[(int64_t)c * P.ldc0 + r];
           D[(int64_t)c * P.ldd + r] = val;
@@ -310,6 +323,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
   const float* __restrict__ A = (const float*)P.A;
   const float* __restrict__ B = (const float*)P.B;
   const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_lo = fl & G_A_MLO, b_lo = fl & G_B_MLO;
   const bool a_edge = I0 + BM > P.M, b_edge = J0 + BN > P.N;
 
   f32x16 acc[MB][NB];
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
 #pragma unroll
       for (int i = 0; i < AK; ++i) {
         float x = ra[i][q];
-        if (am) x = select_op(x, r, k0 + akg * AK + i, a_lu, a_up, P.M, 1 << 30);
+        if (am) x = select_op(x, r, k0 + akg * AK + i, a_lu, a_up, a_lo, P.M, 1 << 30);
         h[i] = (__bf16)x;
         if (SPLIT) l[i] = (__bf16)(x - (float)h[i]);
       }
@@ -369,7 +383,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         float x = rb[2 * j + e / 4][e % 4];
-        if (bm) x = select_op(x, k0 + bkg * BKT + 8 * j + e, bc, b_lu, b_up, 1 << 30, P.N);
+        if (bm) x = select_op(x, k0 + bkg * BKT + 8 * j + e, bc, b_lu, b_up, b_lo, 1 << 30, P.N);
         h[e] = (__bf16)x;
         if (SPLIT) l[e] = (__bf16)(x - (float)h[e]);
       }
@@ -378,8 +392,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_bf16(const GemmProb* __re
     }
   };
   auto stage = [&](int st, int k0) __attribute__((always_inline)) {
-    const bool am = a_edge || ((a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM);
-    const bool bm = b_edge || ((b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN);
+    const bool am = a_edge || ((a_lu || a_up || a_lo) && k0 + BK > I0 && k0 < I0 + BM);
+    const bool bm = b_edge || ((b_lu || b_up || b_lo) && k0 + BK > J0 && k0 < J0 + BN);
     if (am || bm) store_chunk(st, k0, am, bm);
     else store_chunk(st, k0, false, false);
   };
@@ -599,6 +613,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __rest
   const char* A = (const char*)P.A;
   const char* B = (const char*)P.B;
   const bool a_lu = fl & G_A_MLU, a_up = fl & G_A_MUP, b_lu = fl & G_B_MLU, b_up = fl & G_B_MUP;
+  const bool a_lo = fl & G_A_MLO, b_lo = fl & G_B_MLO;
 
   f32x16 acc[MB][NB];
 #pragma unroll
@@ -632,18 +647,18 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_gemm_dl(const GemmProb* __rest
     int st = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
       __syncthreads();   // chunk k0 has landed; every wave is done with the other stage
-      const bool am = (a_lu || a_up) && k0 + BK > I0 && k0 < I0 + BM;
-      const bool bm = (b_lu || b_up) && k0 + BK > J0 && k0 < J0 + BN;
+      const bool am = (a_lu || a_up || a_lo) && k0 + BK > I0 && k0 < I0 + BM;
+      const bool bm = (b_lu || b_up || b_lo) && k0 + BK > J0 && k0 < J0 + BN;
       if (am || bm) {
         if (am)
           for (int i = tid; i < BK * BM; i += 64 * NW) {
             const int k = i / BM, m = i % BM;
-            As[st][i] = select_op(As[st][i], I0 + m, k0 + k, a_lu, a_up, 1 << 30, 1 << 30);
+            As[st][i] = select_op(As[st][i], I0 + m, k0 + k, a_lu, a_up, a_lo, 1 << 30, 1 << 30);
           }
         if (bm)
           for (int i = tid; i < BN * BK; i += 64 * NW) {
             const int n = i / BK, k = 4 * (((i % BK) >> 2) ^ (n & 7)) + (i & 3);
-            Bs[st][i] = select_op(Bs[st][i], k0 + k, J0 + n, b_lu, b_up, 1 << 30, 1 << 30);
+            Bs[st][i] = select_op(Bs[st][i], k0 + k, J0 + n, b_lu, b_up, b_lo, 1 << 30, 1 << 30);
           }
         __syncthreads();
       }

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvProb* __restrict__ probs
   const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = r0 + lane;
   const int fl = P.flags;
-  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP;
+  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP, mlo = fl & V_A_MLO;
   const T* __restrict__ A = (const T*)P.A + r;
   const int64_t lda = P.lda;
   const int split = P.split;
@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvProb* __restrict__ probs
       double av = (double)a[u];
       if (mlu) av = r > cc ? av : (r == cc ? 1.0 : 0.0);
       if (mup) av = r <= cc ? av : 0.0;
+      if (mlo) av = r >= cc ? av : 0.0;
 #pragma unroll
       for (int j = 0; j < R; ++j) acc[j] += av * xval(cc, j);
     }
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvProb* __restrict__ probs
     double av = (double)A[(int64_t)c * lda];
     if (mlu) av = r > c ? av : (r == c ? 1.0 : 0.0);
     if (mup) av = r <= c ? av : 0.0;
+    if (mlo) av = r >= c ? av : 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) acc[j] += av * xval(c, j);
   }
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ pro
   const int q = lane / LPC;             // column slot of this lane
   const int rl = (lane % LPC) * VEC;    // first local row of this lane
   const int fl = P.flags;
-  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP;
+  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP, mlo = fl & V_A_MLO;
   const T* __restrict__ A = (const T*)P.A + r0 + rl;
   const int64_t lda = P.lda;
   const int split = P.split;
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ pro
       double av = (double)a[e];
       if (mlu) av = rr > cc ? av : (rr == cc ? 1.0 : 0.0);
       if (mup) av = rr <= cc ? av : 0.0;
+      if (mlo) av = rr >= cc ? av : 0.0;
 #pragma unroll
       for (int j = 0; j < R; ++j) acc[e][j] += av * xv[j];
     }
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(256) void k_gemv_w(const GemvProb* __restrict__ pro
           double av = (double)a[u][e];
           if (mlu) av = rr > cc ? av : (rr == cc ? 1.0 : 0.0);
           if (mup) av = rr <= cc ? av : 0.0;
+          if (mlo) av = rr >= cc ? av : 0.0;
 #pragma unroll
           for (int j = 0; j < R; ++j) acc[e][j] += av * xv[j];
         }

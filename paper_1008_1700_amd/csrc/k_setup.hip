@@ -106,41 +106,57 @@ __global__ void k_zero_spike_rhs(int p, int t, const BlockInfo* __restrict__ blo
   }
 }
 
+// Entries of A into the tile layout of their block: A_kk into diagonal tile
+// k, A_{k,k+1} (lower triangular, diagonal included) into the lower half of
+// pair k and A_{k+1,k} (upper triangular) into its upper half (a pair is a
+// t x (t+1) column-major array holding both triangles: lower(i, j) at
+// i + j t, upper(i, j) at i + (j + 1) t).  Coupling entries (columns of the
+// neighbouring blocks) become the right-hand sides of the spike solves:
+// into the spike array (rhs == null), or into the compact store rhs, one
+// pair per block with the left coupling C_i (rows of block i against the
+// last t columns of block i-1, upper triangular) in the upper half and the
+// right coupling B_i (the last t rows against the first t columns of block
+// i+1, lower triangular) in the lower half.
 template <typename T>
 __global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ part,
                           const BlockInfo* __restrict__ blocks, const int64_t* __restrict__ row_ptr,
                           const int32_t* __restrict__ col, const double* __restrict__ val,
-                          T* __restrict__ tiles, T* __restrict__ spikes,
+                          T* __restrict__ tiles, T* __restrict__ spikes, T* __restrict__ rhs,
                           unsigned long long* __restrict__ colnorm, unsigned int* __restrict__ flags) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int blk = find_block(part, p, r);
   const BlockInfo B = blocks[blk];
-  const int64_t tt = (int64_t)t * t;
+  const int64_t tt = (int64_t)t * t, pt = tt + t;
   const int64_t lr = B.pad + (r - B.s);
   const int64_t kr = lr / t, rr = lr % t;
   T* __restrict__ G = spikes + B.goff;
+  T* __restrict__ W = tiles + B.tiles;
   for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
     const int64_t c = col[q];
     const double v = val[q];
     if (c >= B.s && c < B.s + B.n) {
       const int64_t lc = B.pad + (c - B.s);
       const int64_t kc = lc / t, cc = lc % t;
-      int64_t tile;
-      if (kc == kr) tile = B.tiles + kr;                    // A_kk
-      else if (kc == kr + 1) tile = B.tiles + 2 * B.T - 1 + kr;  // A_{k,k+1}
-      else if (kc == kr - 1) tile = B.tiles + B.T + kc;     // A_{k+1,k}
+      int64_t idx;
+      if (kc == kr) idx = kr * tt + cc * t + rr;                                    // A_kk
+      else if (kc == kr + 1 && rr >= cc) idx = B.T * tt + kr * pt + cc * t + rr;      // A_{k,k+1}
+      else if (kc == kr - 1 && rr <= cc) idx = B.T * tt + kc * pt + t + cc * t + rr;  // A_{k+1,k}
       else { atomicOr(flags, 8u); continue; }
-      tiles[tile * tt + cc * t + rr] += (T)v;
+      W[idx] += (T)v;
     } else if (c < B.s) {
       const int64_t jj = c - (B.s - t);
-      if (jj < 0) { atomicOr(flags, 8u); continue; }
-      G[jj * B.N + lr] += (T)v;
+      const int64_t ir = r - B.s;
+      if (jj < 0 || ir >= t || ir > jj) { atomicOr(flags, 8u); continue; }
+      if (rhs) rhs[(int64_t)blk * pt + t + jj * t + ir] += (T)v;
+      else G[jj * B.N + lr] += (T)v;
       atomicMax(&colnorm[(int64_t)blk * 2 * t + jj], (unsigned long long)__double_as_longlong(fabs(v)));
     } else {
       const int64_t jj = c - (B.s + B.n);
-      if (jj >= t) { atomicOr(flags, 8u); continue; }
-      G[(t + jj) * B.N + lr] += (T)v;
+      const int64_t ir = r - (B.s + B.n - t);
+      if (jj >= t || ir < jj) { atomicOr(flags, 8u); continue; }
+      if (rhs) rhs[(int64_t)blk * pt + jj * t + ir] += (T)v;
+      else G[(t + jj) * B.N + lr] += (T)v;
       atomicMax(&colnorm[(int64_t)blk * 2 * t + t + jj],
                 (unsigned long long)__double_as_longlong(fabs(v)));
     }
@@ -152,7 +168,7 @@ template <typename T>
 __global__ void k_pad_identity(int p, int t, const BlockInfo* __restrict__ blocks, T* __restrict__ tiles) {
   const BlockInfo B = blocks[blockIdx.x];
   for (int64_t i = threadIdx.x; i < B.pad; i += blockDim.x)
-    tiles[B.tiles * (int64_t)t * t + i * t + i] = T(1);
+    tiles[B.tiles + i * t + i] = T(1);
 }
 
 // Dropping rule (one workgroup per block): column k of R_i is kept iff
@@ -161,7 +177,7 @@ __global__ void k_pad_identity(int p, int t, const BlockInfo* __restrict__ block
 template <typename T>
 __global__ void k_mask(int p, int t, double delta, const BlockInfo* __restrict__ blocks,
                        const unsigned long long* __restrict__ colnorm, double* __restrict__ mask,
-                       T* __restrict__ spikes) {
+                       T* __restrict__ spikes, T* __restrict__ rhs) {
   __shared__ double red[256];
   const int blk = blockIdx.x;
   const BlockInfo B = blocks[blk];
@@ -184,7 +200,14 @@ __global__ void k_mask(int p, int t, double delta, const BlockInfo* __restrict__
     if (!top && blk == p - 1) continue;
     const int64_t q = top ? (int64_t)2 * (blk - 1) * t + j : (int64_t)(2 * blk + 1) * t + (j - t);
     mask[q] = keep ? 1.0 : 0.0;
-    if (!keep) {
+    if (!keep && rhs) {
+      // column j of C_i (upper half, rows 0..j) or column j - t of B_i
+      // (lower half, rows j - t .. t-1) in the compact store
+      const int64_t pt = (int64_t)t * t + t;
+      T* P = rhs + (int64_t)blk * pt;
+      if (top) for (int64_t r = 0; r <= j; ++r) P[t + (int64_t)j * t + r] = T(0);
+      else for (int64_t r = j - t; r < t; ++r) P[(int64_t)(j - t) * t + r] = T(0);
+    } else if (!keep) {
       const int64_t r0 = top ? 0 : B.N - t;
       const int64_t r1 = top ? min((int64_t)2 * t, B.N) : B.N;
       for (int64_t r = r0; r < r1; ++r) G[(int64_t)j * B.N + r] = T(0);
@@ -226,27 +249,27 @@ void fill_u64(unsigned long long* ptr, int64_t count, unsigned long long v, hipS
 
 void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, const BlockInfo* blocks,
                    const int64_t* row_ptr, const int32_t* col, const double* val, void* tiles,
-                   void* spikes, unsigned long long* colnorm, unsigned int* flags, hipStream_t s) {
+                   void* spikes, void* rhs, unsigned long long* colnorm, unsigned int* flags, hipStream_t s) {
   const int64_t nb = (n + 255) / 256;
   if (dtype == 0) {
     hipLaunchKernelGGL(k_scatter<double>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
-                       row_ptr, col, val, (double*)tiles, (double*)spikes, colnorm, flags);
+                       row_ptr, col, val, (double*)tiles, (double*)spikes, (double*)rhs, colnorm, flags);
     hipLaunchKernelGGL(k_pad_identity<double>, dim3(p), dim3(256), 0, s, p, t, blocks, (double*)tiles);
   } else {
     hipLaunchKernelGGL(k_scatter<float>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
-                       row_ptr, col, val, (float*)tiles, (float*)spikes, colnorm, flags);
+                       row_ptr, col, val, (float*)tiles, (float*)spikes, (float*)rhs, colnorm, flags);
     hipLaunchKernelGGL(k_pad_identity<float>, dim3(p), dim3(256), 0, s, p, t, blocks, (float*)tiles);
   }
 }
 
 void setup_mask(int dtype, int p, int t, double delta, const BlockInfo* blocks,
-                const unsigned long long* colnorm, double* mask, void* spikes, hipStream_t s) {
+                const unsigned long long* colnorm, double* mask, void* spikes, void* rhs, hipStream_t s) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_mask<double>, dim3(p), dim3(256), 0, s, p, t, delta, blocks, colnorm, mask,
-                       (double*)spikes);
+                       (double*)spikes, (double*)rhs);
   else
     hipLaunchKernelGGL(k_mask<float>, dim3(p), dim3(256), 0, s, p, t, delta, blocks, colnorm, mask,
-                       (float*)spikes);
+                       (float*)spikes, (float*)rhs);
 }
 
 void setup_row_thresh(int64_t n, int p, int64_t Np, const int64_t* part, const BlockInfo* blocks,

@@ -439,6 +439,56 @@ __global__ __launch_bounds__(256) void k_csr_resid(int64_t n, const int64_t* __r
   }
 }
 
+// Right-hand side of the re-solved retrieval (step 6.5 written as
+// z = D~^{-1}(y - R~ z)): yp = y - R~ z in the padded block layout, for k of
+// R columns (columns k..R-1 and the padding rows are zero).  R~ z takes the
+// off-block entries of each row of A against the reduced solution z^ (the
+// candidate layout: interface j owns the 2t columns [s_{j+1} - t,
+// s_{j+1} + t), t after the end of block j), masked to the index set c, so
+// that dropped columns of R do not contribute.
+template <int R>
+__global__ __launch_bounds__(256) void k_coupling_rhs(int64_t Np, int p, int t, int k,
+                                                      const BlockInfo* __restrict__ blocks,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ y, int64_t ldy,
+                                                      const double* __restrict__ zh, int64_t m,
+                                                      const double* __restrict__ mask, double* __restrict__ yp) {
+  for (int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pr < Np;
+       pr += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = p - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (blocks[mid].voff <= pr) lo = mid; else hi = mid - 1;
+    }
+    const BlockInfo B = blocks[lo];
+    const int64_t lr = pr - B.voff;
+    double acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = 0.0;
+    if (lr >= B.pad) {
+      const int64_t r = B.s + (lr - B.pad);
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (j < k) acc[j] = y[r + j * ldy];
+      for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+        const int64_t c = col[q];
+        int64_t idx;
+        if (c < B.s) idx = (int64_t)2 * (lo - 1) * t + (c - (B.s - t));
+        else if (c >= B.s + B.n) idx = (int64_t)2 * lo * t + t + (c - (B.s + B.n));
+        else continue;
+        const double w = val[q] * mask[idx];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (j < k) acc[j] -= w * zh[idx + j * m];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) yp[pr + j * Np] = acc[j];
+  }
+}
+
 // Reduce [W][R][4] residual partials to out[R][4] (max, sum, max, sum).
 template <int R>
 __global__ void k_resid_reduce(int W, const double* __restrict__ part, double* __restrict__ out) {
@@ -588,6 +638,12 @@ void residual_norms_cols(int64_t n, int k, const int64_t* row_ptr, const int32_t
               R ? R + (int64_t)j0 * ldr : nullptr, ldr, part, W, out + 4 * j0, s);
     j0 += g;
   }
+}
+void coupling_rhs(int64_t Np, int R, int k, int p, int t, const BlockInfo* blocks, const int64_t* row_ptr,
+                  const int32_t* col, const double* val, const double* y, int64_t ldy, const double* zh, int64_t m,
+                  const double* mask, double* yp, hipStream_t s) {
+  DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_coupling_rhs<RR>, dim3(grid_for(Np)), dim3(256), 0, s, Np, p, t, k, blocks,
+                                        row_ptr, col, val, y, ldy, zh, m, mask, yp));
 }
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s) {

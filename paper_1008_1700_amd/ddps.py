@@ -45,6 +45,9 @@ class ddps_options(ctypes.Structure):
         ("factor_streams", ctypes.c_int32),
         ("factor_graph", ctypes.c_int32),
         ("inner_prec", ctypes.c_int32),
+        ("retrieval", ctypes.c_int32),
+        ("norm", ctypes.c_int32),
+        ("work_slots", ctypes.c_int32),
     ]
 
 
@@ -394,7 +397,7 @@ class Solver:
 
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
-                 mem_budget=0, streams=0, graph=False, inner_prec=0):
+                 mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -411,6 +414,9 @@ class Solver:
         o.factor_streams = int(streams)
         o.factor_graph = 1 if graph else 0
         o.inner_prec = int(inner_prec)
+        o.retrieval = int(retrieval)
+        o.norm = int(norm)
+        o.work_slots = int(work_slots)
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

@@ -34,3 +34,10 @@ def oracle_prec(d, delta=0.0):
     from oracle import ddps_oracle as O
     A = d["A"]
     return O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"], delta)
+
+
+def maxrel(a, b):
+    """Element-wise bar: max |a - b| over max |b| (every entry is held to the
+    largest one's scale, so a wrong small entry is not averaged away)."""
+    mb = np.max(np.abs(b)) if np.size(b) else 0.0
+    return float(np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0)) if np.size(b) else 0.0

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from tests.gpu_util import dev_vec, host, make_solver, oracle_prec, relerr, torch_cuda
+from tests.gpu_util import dev_vec, host, make_solver, maxrel, oracle_prec, relerr, torch_cuda
 from workloads import configs, pde
 
 pytestmark = pytest.mark.gpu
@@ -69,12 +69,13 @@ def test_c1_factor_tiles(c1, c1_solver, blk):
         di, lp, up = _expected_tiles(fac, t, k)
         ddps.ddps_get_tile(c1_solver.h, blk, k, 0, buf)
         got = host(buf).reshape(t, t).T
-        assert relerr(got, di) <= 1e-11, (blk, k)
+        # unpivoted LU is unique: entry by entry
+        assert maxrel(got, di) <= 1e-12, (blk, k)
         if lp is not None:
             ddps.ddps_get_tile(c1_solver.h, blk, k, 1, buf)
-            assert relerr(host(buf).reshape(t, t).T, lp) <= 1e-11
+            assert maxrel(host(buf).reshape(t, t).T, lp) <= 1e-12
             ddps.ddps_get_tile(c1_solver.h, blk, k, 2, buf)
-            assert relerr(host(buf).reshape(t, t).T, up) <= 1e-11
+            assert maxrel(host(buf).reshape(t, t).T, up) <= 1e-12
 
 
 @pytest.mark.parametrize("blk", [0, 1, 3])
@@ -92,7 +93,7 @@ def test_c1_spikes(c1, c1_solver, c1_oracle, blk):
     for j, col in enumerate(ci):
         q = col - (lo - t) if col < lo else t + (col - hi)
         exp[:, q] = Gi[:, j]
-    assert relerr(got, exp) <= 1e-11
+    assert maxrel(got, exp) <= 1e-12
 
 
 def test_c1_block_solve(c1, c1_solver, c1_oracle):

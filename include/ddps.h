@@ -251,20 +251,24 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row);
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy);
 
 /* Autotuner of the execution form.  It times ddps_factor on the device for
- * stream groups {1, 2, 3, 4, 6, 8} (at most p) and the fixed tile policies (0, 1,
- * 2, 4, 5 for the bf16 dtypes; 0, 1 otherwise), and takes the fewest groups
- * within 3% of the fastest form.  For every group count within 10% of the
- * fastest it then times each GEMM launch of the factorisation under each
- * fixed policy and builds policy 3 from the fastest tile of each launch; the
- * fewest groups within 3% of the fastest such form are kept if they beat the
- * fixed form.  The choice, with policy 3's
- * per-launch tiles, is recorded in the JSON file cache_path (may be NULL)
- * under a key made of the GPU architecture, factor dtype, tile size t, p and
- * the largest tile-row count; a later call with the same key takes the
- * cached choice without timing.  Host outputs (may be NULL): chosen streams,
- * tile policy and its factor time in milliseconds.  The handle is left
- * factored with the chosen form. */
-int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy,
+ * stream groups {1, 2, 3, 4, 6, 8} (at most p, and at most the workspace
+ * slots with retrieval 1) and the fixed tile policies (0, 1, 2, 4, 5 for the
+ * bf16 dtypes; 0, 1 otherwise), and takes the fewest groups within 3% of the
+ * fastest form.  For every group count within 10% of the fastest it then
+ * times each GEMM launch of the factorisation under each fixed policy and
+ * builds policy 3 from the fastest tile of each launch; the fewest groups
+ * within 3% of the fastest such form are kept if they beat the fixed form.
+ * budget_s > 0 bounds the search: once that many seconds have passed no
+ * further form is timed and the best form so far is taken (the first form
+ * is always timed).  One progress line per timed form goes to stderr.  The
+ * choice, with policy 3's per-launch tiles, is recorded in the JSON file
+ * cache_path (may be NULL) under a key made of the GPU architecture, factor
+ * dtype, tile size t, p, the largest tile-row count and (retrieval 1) the
+ * workspace slots; a later call with the same key takes the cached choice
+ * without timing.  Host outputs (may be NULL): chosen streams, tile policy
+ * and its factor time in milliseconds.  The handle is left factored with the
+ * chosen form. */
+int ddps_autotune(ddps_handle h, const char* cache_path, double budget_s, int32_t* streams, int32_t* tile_policy,
                   double* factor_ms);
 
 /* Per-kernel timing for roofline reporting.  ddps_timing_enable(h, kind, 1)
@@ -394,6 +398,25 @@ int ddps_residual_norms(int64_t n, int32_t k, const int64_t* row_ptr, const int3
 int ddps_residual_norms_noalloc(int64_t n, int32_t k, const int64_t* row_ptr, const int32_t* col,
                                 const double* val, const double* X, int64_t ldx, const double* F, int64_t ldf,
                                 double* R, int64_t ldr, double* norms, void* stream);
+
+/* Learned guess in every preconditioner application.  Attaches a network
+ * (d_in >= 4t + 2, d_out = 2t, max_batch >= R (p-1) for R = max_rhs rounded
+ * up to 1, 2, 4 or 8; created on the handle's stream) to the handle; NULL
+ * detaches it.  While attached, each application of Figure 2 starts the
+ * reduced solve of step 6.3 from the best of three vectors per right-hand
+ * side, judged by ||g^ - G^ z0||_2 on c: z0 = 0, z0 = g^ (since
+ * G^ = I + G(c,c)), and z0 = g^ + s_j Y_j per interface j, Y the network's
+ * output for the input row [r_j / s_j, g^_j / q_j, 0, 0] (r = g^ - G^ g^,
+ * s_j = max |r_j|, q_j = max |g^_j|; the layout of ddps_guess_features with
+ * z^prev = g^).  A vector set with ddps_set_guess is not used meanwhile.
+ * The network is used, not owned: keep it alive while attached.  Buffers for
+ * the network's inputs and outputs are allocated here (not during solves).
+ * Errors: DDPS_E_ARG (shape or stream mismatch), DDPS_E_NOMEM. */
+int ddps_set_guess_model(ddps_handle h, ddps_mlp net);
+
+/* Host int64[3]: reduced solves started so far from z0 = 0, from g^ and
+ * from the network, over the handle's lifetime (with a network attached). */
+int ddps_guess_counts(ddps_handle h, int64_t* counts);
 
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);

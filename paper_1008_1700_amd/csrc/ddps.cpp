@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -159,6 +160,11 @@ struct ddps_ctx {
   int W1 = 0;
   bool factored = false;
   int guess_k = 0;
+  // learned guess in every preconditioner application (ddps_set_guess_model)
+  ddps_mlp gnet = nullptr;
+  int gnet_din = 0;
+  float *d_gX = nullptr, *d_gS = nullptr, *d_gY = nullptr;
+  int64_t guess_counts[3] = {0, 0, 0};   // reduced solves started from 0, from g^, from the network
   // last solve
   int last_k = 0;
   // timing
@@ -1148,6 +1154,61 @@ int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::v
   return DDPS_OK;
 }
 
+int dots(ddps_ctx* h, int64_t len, const double* a0, const double* b0, const double* a1, const double* b1,
+         std::vector<double>& d0, std::vector<double>& d1);
+
+// Learned starting vector of the reduced solve of one application (a network
+// attached with ddps_set_guess_model).  Three candidates per column, judged
+// by the reduced residual ||g^ - G^ z0||_2 on c: z0 = 0; z0 = g^ (G^ = I +
+// G(c,c), so g^ is the zero-order approximation of z^); and the network's
+// correction of g^, z0 = g^ + s_j net([r_j/s_j, g^_j/q_j, 0, 0]) per
+// interface j, r = g^ - G^ g^ the residual of g^.  The smallest residual wins
+// and is left in d_guess.  Two reduced products, one network pass and one
+// host synchronisation.
+int learned_start(ddps_ctx* h, int k) {
+  const int R = h->R;
+  const int64_t m = h->m;
+  hipStream_t s = h->stream;
+  const int nif = h->p - 1;
+  Coef3 cf{};
+  for (int j = 0; j < R; ++j) {
+    cf.a[j] = 1.0;
+    cf.b[j] = -1.0;
+  }
+  // residual of the zero-order candidate g^
+  HIPCHK(hipMemcpyAsync(h->d_zh, h->d_gh, sizeof(double) * m * R, hipMemcpyDeviceToDevice, s));
+  run_launch(h, h->l_zv, R, m, m, nullptr, nullptr, nullptr, TK_RSPMV);
+  lincomb(R, m, cf, h->d_gh, h->d_v, nullptr, h->d_r, s);
+  vec_apply_mask(m, R, h->d_mask, h->d_r, s);
+  // the network's candidate
+  guess_features(nif, k, 2 * h->t, h->gnet_din, h->d_r, h->d_gh, h->d_mask, 0.0, 0.0, h->d_gX, h->d_gS, s);
+  int rc = ddps_mlp_forward(h->gnet, k * nif, h->d_gX, h->d_gY);
+  if (rc) return rc;
+  guess_compose(m * k, m, 2 * h->t, h->d_gh, h->d_gY, h->d_gS, h->d_mask, h->d_guess, s);
+  HIPCHK(hipMemcpyAsync(h->d_zh, h->d_guess, sizeof(double) * m * k, hipMemcpyDeviceToDevice, s));
+  run_launch(h, h->l_zv, R, m, m, nullptr, nullptr, nullptr, TK_RSPMV);
+  lincomb(R, m, cf, h->d_gh, h->d_v, nullptr, h->d_rt, s);
+  vec_apply_mask(m, R, h->d_mask, h->d_rt, s);
+  std::vector<double> nb, nl, ng, unused;
+  if ((rc = dots(h, m, h->d_r, h->d_r, h->d_rt, h->d_rt, nb, nl))) return rc;
+  if ((rc = dots(h, m, h->d_gh, h->d_gh, nullptr, nullptr, ng, unused))) return rc;
+  for (int j = 0; j < k; ++j) {
+    double* col = h->d_guess + (int64_t)j * m;
+    if (ng[j] <= nb[j] && ng[j] <= nl[j]) {
+      fill_f64(col, m, 0.0, s);
+      ++h->guess_counts[0];
+    } else if (nb[j] <= nl[j]) {
+      HIPCHK(hipMemcpyAsync(col, h->d_gh + (int64_t)j * m, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+      ++h->guess_counts[1];
+    } else {
+      ++h->guess_counts[2];
+    }
+  }
+  if (k < R) fill_f64(h->d_guess + (int64_t)k * m, m * (R - k), 0.0, s);
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
 // z = P^{-1} y (k columns, device, leading dims ldy/ldz).  Reduced vectors
 // are left in d_gh / d_zh.
 int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int64_t ldz, double inner_tol,
@@ -1160,6 +1221,10 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
   rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
   if (rc) return rc;
   vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_gh, s);
+  if (h->gnet && h->m > 0) {
+    if ((rc = learned_start(h, k))) return rc;
+    use_guess = 1;
+  }
   std::vector<int> st;
   rc = inner_solve(h, k, use_guess, inner_tol, h->opt.inner_maxit, iters, st);
   if (rc) return rc;
@@ -1457,6 +1522,9 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   } else {
     if (need >= budget) return fail(DDPS_E_NOMEM);
     int64_t fit = (int64_t)((budget - need) / slot_bytes);
+    // above 32 slots, a multiple of 32: the launch sequence (and so the
+    // autotuner's cache key) then does not move with a few GB of free memory
+    if (fit > 32) fit -= fit % 32;
     fit = std::min<int64_t>(fit, p);
     if (o.work_slots > 0) fit = std::min<int64_t>(fit, o.work_slots);
     if (fit < 1) return fail(DDPS_E_NOMEM);
@@ -1861,6 +1929,38 @@ int ddps_set_guess(ddps_handle h, const double* zhat0, int32_t k) {
   return DDPS_OK;
 }
 
+int ddps_set_guess_model(ddps_handle h, ddps_mlp net) {
+  if (!h) return DDPS_E_ARG;
+  if (!net) {
+    h->gnet = nullptr;
+    return DDPS_OK;
+  }
+  int din = 0, dout = 0, mb = 0;
+  hipStream_t ns = nullptr;
+  if (mlp_shape(net, &din, &dout, &mb, &ns) || din < 4 * h->t + 2 || dout != 2 * h->t ||
+      (int64_t)mb < (int64_t)h->R * (h->p - 1) || ns != h->stream)
+    return DDPS_E_ARG;
+  if (h->m == 0) return DDPS_OK;
+  if (din != h->gnet_din) {
+    const int64_t rows = (int64_t)h->R * (h->p - 1);
+    for (float* q : {h->d_gX, h->d_gS, h->d_gY}) h->free_ptr(q);
+    h->d_gX = h->d_gS = h->d_gY = nullptr;
+    int rc;
+    if ((rc = h->alloc(h->d_gX, rows * din)) || (rc = h->alloc(h->d_gS, rows)) ||
+        (rc = h->alloc(h->d_gY, rows * dout)))
+      return rc;
+    h->gnet_din = din;
+  }
+  h->gnet = net;
+  return DDPS_OK;
+}
+
+int ddps_guess_counts(ddps_handle h, int64_t* counts) {
+  if (!h || !counts) return DDPS_E_ARG;
+  for (int q = 0; q < 3; ++q) counts[q] = h->guess_counts[q];
+  return DDPS_OK;
+}
+
 int ddps_reduced_layout(ddps_handle h, int64_t* m, int64_t* c, double* mask, int32_t* t, int32_t* b) {
   if (!h) return DDPS_E_ARG;
   if (m) *m = h->m;
@@ -2118,7 +2218,12 @@ std::string tune_key(ddps_ctx* h) {
   }
   static const char* dt[] = {"f64", "f32", "bf16x3", "bf16"};
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s/%s/t%d/p%d/T%d", arch.c_str(), dt[h->gdt], h->t, h->p, h->Tmax);
+  // the tips-only form's launch sequence depends on its workspace slots
+  if (h->tips_only)
+    std::snprintf(buf, sizeof(buf), "%s/%s/t%d/p%d/T%d/tips%lld", arch.c_str(), dt[h->gdt], h->t, h->p, h->Tmax,
+                  (long long)h->nslots);
+  else
+    std::snprintf(buf, sizeof(buf), "%s/%s/t%d/p%d/T%d", arch.c_str(), dt[h->gdt], h->t, h->p, h->Tmax);
   return buf;
 }
 
@@ -2229,6 +2334,11 @@ int time_gemm_launches(ddps_ctx* h, std::vector<float>& out) {
 // Policy 3 for `groups` stream groups: time every factor GEMM launch under
 // each fixed policy, keep per launch the tile of the fastest, and time the
 // resulting schedule (*ms).  Leaves the handle factored with policy 3.
+// Seconds since `t0` (host clock) for the autotuner's budget and progress.
+double secs_since(const std::chrono::steady_clock::time_point& t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
   // fixed policies 0, 1, 2, 4 and 5 ask for tile modes 1, 0, 2, 3 and 4
   static const int8_t mode_of_policy[5] = {1, 0, 2, 3, 4};
@@ -2260,9 +2370,14 @@ int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
 }
 }  // namespace
 
-int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32_t* tile_policy, double* factor_ms) {
+int ddps_autotune(ddps_handle h, const char* cache_path, double budget_s, int32_t* streams, int32_t* tile_policy,
+                  double* factor_ms) {
   if (!h) return DDPS_E_ARG;
   const std::string key = tune_key(h);
+  const auto t0 = std::chrono::steady_clock::now();
+  // once the budget is spent no further form is timed: the best one so far
+  // stands (the first form is always timed)
+  auto over = [&]() { return budget_s > 0.0 && secs_since(t0) > budget_s; };
   int bs = 0, bq = 0;
   double bms = 0;
   int rc;
@@ -2280,12 +2395,15 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
     if (h->gdt >= 2) pols = {0, 1, 2, 4, 5};
     for (int q : pols)
       for (int g : {1, 2, 3, 4, 6, 8}) {
-        if (g > h->p) continue;
+        if (g > h->p || (h->tips_only && g > h->nslots)) continue;
+        if (!tried.empty() && over()) break;
         if ((rc = ddps_set_execution(h, g, 0, q))) return rc;
         if ((rc = ddps_factor(h))) return rc;       // warm-up
         if ((rc = ddps_factor(h))) return rc;
         tried.push_back({(double)g, (double)q, h->t_factor_ms});
         best = std::min(best, h->t_factor_ms);
+        std::fprintf(stderr, "ddps_autotune %s: %d groups, policy %d: %.2f ms (%.1f s)\n", key.c_str(), g, q,
+                     h->t_factor_ms, secs_since(t0));
       }
     bms = 1e300;
     int bg = 1 << 30;
@@ -2325,11 +2443,14 @@ int ddps_autotune(ddps_handle h, const char* cache_path, int32_t* streams, int32
     std::vector<std::vector<int8_t>> choice;
     double best3 = 1e300;
     for (int g : cand) {
+      if (over()) break;
       double ms3 = 0;
       if ((rc = tune_launch_modes(h, g, &ms3))) return rc;
       per.push_back({g, ms3});
       choice.push_back(h->mode_choice);
       best3 = std::min(best3, ms3);
+      std::fprintf(stderr, "ddps_autotune %s: %d groups, per-launch tiles: %.2f ms (%.1f s)\n", key.c_str(), g, ms3,
+                   secs_since(t0));
     }
     int pick = -1;
     for (size_t i = 0; i < per.size(); ++i)

@@ -6,7 +6,12 @@
 
 #include <algorithm>
 
+struct ddps_mlp_ctx;
+
 namespace ddps {
+
+// Shape and stream of a network (for the handle's learned guess).
+int mlp_shape(const ddps_mlp_ctx* M, int* d_in, int* d_out, int* max_batch, hipStream_t* stream);
 
 enum MlpEpilogue : int {
   MLP_BIAS = 1,        // add bias[n]

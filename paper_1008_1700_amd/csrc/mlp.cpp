@@ -101,6 +101,17 @@ int backward(ddps_mlp_ctx* M, int B, const float* T, double* loss) {
 
 }  // namespace
 
+namespace ddps {
+int mlp_shape(const ddps_mlp_ctx* M, int* d_in, int* d_out, int* max_batch, hipStream_t* stream) {
+  if (!M) return DDPS_E_ARG;
+  *d_in = M->d_in;
+  *d_out = M->d_out;
+  *max_batch = M->max_batch;
+  *stream = M->stream;
+  return DDPS_OK;
+}
+}  // namespace ddps
+
 extern "C" {
 
 int ddps_mlp_create(ddps_mlp* out, int32_t d_in, int32_t hidden, int32_t d_out, int32_t max_batch, uint64_t seed,

@@ -96,7 +96,8 @@ _SIGS = {
     "ddps_block_shape": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "ddps_last_singular": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
     "ddps_set_execution": (_I32, [_P, _I32, _I32, _I32]),
-    "ddps_autotune": (_I32, [_P, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
+    "ddps_autotune": (_I32, [_P, ctypes.c_char_p, _D, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                             ctypes.POINTER(_D)]),
     "ddps_timing_enable": (_I32, [_P, _I32, _I32]),
     "ddps_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D),
                                 ctypes.POINTER(_D)]),
@@ -115,6 +116,8 @@ _SIGS = {
     "ddps_mlp_gradients": (_I32, [_P, _I32, _P, _P, _P, ctypes.POINTER(_D)]),
     "ddps_mlp_destroy": (None, [_P]),
     "ddps_memory": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "ddps_set_guess_model": (_I32, [_P, _P]),
+    "ddps_guess_counts": (_I32, [_P, ctypes.POINTER(_I64)]),
     "ddps_residual_norms": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D), _P]),
     "ddps_residual_norms_noalloc": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D),
                                            _P]),
@@ -267,12 +270,13 @@ def ddps_set_execution(h, streams=0, graph=False, tile_policy=0):
     _chk(lib().ddps_set_execution(h, int(streams), 1 if graph else 0, int(tile_policy)), "ddps_set_execution")
 
 
-def ddps_autotune(h, cache_path=None):
+def ddps_autotune(h, cache_path=None, budget_s=0.0):
     s = ctypes.c_int32()
     q = ctypes.c_int32()
     ms = ctypes.c_double()
     path = None if cache_path is None else os.fsencode(cache_path)
-    _chk(lib().ddps_autotune(h, path, ctypes.byref(s), ctypes.byref(q), ctypes.byref(ms)), "ddps_autotune")
+    _chk(lib().ddps_autotune(h, path, float(budget_s), ctypes.byref(s), ctypes.byref(q), ctypes.byref(ms)),
+         "ddps_autotune")
     return dict(streams=s.value, tile_policy=q.value, factor_ms=ms.value)
 
 
@@ -374,6 +378,16 @@ def ddps_residual_norms(row_ptr, col, val, X, F, R=None, stream=None):
                                    ctypes.c_void_p(stream))
     _chk(rc, "ddps_residual_norms")
     return out.reshape(k, 4)
+
+
+def ddps_set_guess_model(h, net):
+    _chk(lib().ddps_set_guess_model(h, net), "ddps_set_guess_model")
+
+
+def ddps_guess_counts(h):
+    c = (_I64 * 3)()
+    _chk(lib().ddps_guess_counts(h, c), "ddps_guess_counts")
+    return dict(zero=c[0], ghat=c[1], learned=c[2])
 
 
 def ddps_memory(h):

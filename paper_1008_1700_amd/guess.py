@@ -198,3 +198,141 @@ def run_sequence(S, values_fn, steps, train_steps, dt, source, tol, hidden=512, 
     finally:
         LG.close()
     return dict(records=recs, loss=hist, train_s=t_train, u=u)
+
+
+class RhsGuess:
+    """Learned guess for one matrix without a time sequence.
+
+    The reduced solution of a right-hand side is z^ = G^^{-1} g^, one linear
+    map for every right-hand side and every preconditioner application of the
+    same factors.  Training pairs come from plain solves of random right-hand
+    sides: the input row of interface j is [r_j / s_j, g^_j / q_j, 0, 0] with
+    r = g^ - G^ g^ the residual of the zero-order guess g^ (G^ = I + G(c,c)),
+    and the target is (z^_j - g^_j) / s_j, z^ the restriction of the solution
+    (exact coupling: the reduced solution is the solution on c).  Once
+    trained, the network is attached to the handle (ddps_set_guess_model),
+    which then tries it in every application, judged against z0 = 0 and
+    z0 = g^ by the reduced residual.
+
+    Orchestration only: every numerical step runs in libddps.so."""
+
+    def __init__(self, h, p, max_rhs, capacity_rhs, hidden=512, seed=0, batch_rows=512, stream=None):
+        import torch
+        self.torch = torch
+        self.h = h
+        self.m, self.t, _ = ddps.ddps_reduced_layout(h)
+        self.nif = p - 1
+        self.d_in = 4 * self.t + 2
+        self.d_out = 2 * self.t
+        self.kmax = max_rhs
+        R = 1 if max_rhs <= 1 else 2 if max_rhs <= 2 else 4 if max_rhs <= 4 else 8
+        self.max_batch = max(batch_rows, R * self.nif)
+        rows = capacity_rhs * self.nif
+        f32 = dict(dtype=torch.float32, device="cuda")
+        f64 = dict(dtype=torch.float64, device="cuda")
+        self.Xd = torch.zeros(rows, self.d_in, **f32)
+        self.Td = torch.zeros(rows, self.d_out, **f32)
+        self.Sd = torch.zeros(rows, **f32)
+        self.ghat = torch.zeros(max_rhs, max(self.m, 1), **f64)
+        self.rb = torch.zeros_like(self.ghat)
+        self.zh = torch.zeros_like(self.ghat)
+        self.rows = 0
+        self.rng = np.random.default_rng(seed)
+        self.net = ddps.ddps_mlp_create(self.d_in, hidden, self.d_out, self.max_batch, seed=seed, stream=stream)
+
+    def record(self, F, X):
+        """Pairs of k right-hand sides F and their solutions X ((k, n)
+        contiguous float64 device tensors) into the dataset."""
+        k = F.shape[0]
+        r0, r1 = self.rows, self.rows + k * self.nif
+        if r1 > self.Xd.shape[0]:
+            raise ValueError("training set full")
+        ddps.ddps_reduced_rhs(self.h, k, F, self.ghat)
+        ddps.ddps_reduced_residual(self.h, k, self.ghat, self.ghat, self.rb)
+        ddps.ddps_guess_features(self.h, k, self.rb, self.ghat, 0.0, 0.0, self.d_in, self.Xd[r0:r1], self.Sd[r0:r1])
+        ddps.ddps_reduced_restrict(self.h, k, X, self.zh)
+        ddps.ddps_guess_target(self.h, k, self.zh, self.ghat, self.Sd[r0:r1], self.Td[r0:r1])
+        self.rows = r1
+
+    def train(self, epochs=100, batch_rows=512, lr=1e-3, time_budget_s=None):
+        """Adam on the recorded pairs (contiguous minibatches in a random
+        order per epoch); returns the mean loss of the first and last epochs
+        and the epochs run (fewer when the time budget runs out)."""
+        import time
+        rows = self.rows
+        if rows == 0:
+            return dict(loss=[], epochs=0)
+        b = max(1, min(batch_rows, self.max_batch, rows))
+        starts = np.arange(0, rows, b)
+        hist = []
+        t0 = time.perf_counter()
+        done = 0
+        for e in range(epochs):
+            last = e == epochs - 1 or (time_budget_s is not None and time.perf_counter() - t0 > time_budget_s)
+            want = last or e == 0
+            tot = 0.0
+            for s0 in self.rng.permutation(starts):
+                s1 = min(rows, s0 + b)
+                loss = ddps.ddps_mlp_train_step(self.net, s1 - s0, self.Xd[s0:s1], self.Td[s0:s1], lr,
+                                                want_loss=want)
+                if want:
+                    tot += loss * (s1 - s0)
+            if want:
+                hist.append(tot / rows)
+            done = e + 1
+            if last:
+                break
+        return dict(loss=hist, epochs=done)
+
+    def attach(self, on=True):
+        ddps.ddps_set_guess_model(self.h, self.net if on else None)
+
+    def close(self):
+        if self.net:
+            ddps.ddps_set_guess_model(self.h, None)
+            ddps.ddps_mlp_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_rhs_guess(S, A, K=32, seed=3, tol=1e-10, hidden=512, epochs=100, lr=1e-3, batch_rows=512,
+                    time_budget_s=None, log=None):
+    """The learned guess of a fixed matrix (the solver S's handle, A its CSR
+    on the host): K random right-hand sides f = A x, x ~ U[-1, 1] from
+    default_rng(seed), solved in batches of S's max_rhs with the plain
+    method, recorded and trained on.  Returns (RhsGuess, stats)."""
+    import time
+    import torch
+    kmax = S.opt.max_rhs
+    G = RhsGuess(S.h, S.p, kmax, K, hidden=hidden, seed=seed, batch_rows=batch_rows, stream=S.stream.cuda_stream)
+    rng = np.random.default_rng(seed)
+    As = A.scipy()
+    t0 = time.perf_counter()
+    solve_ms = 0.0
+    done = 0
+    while done < K:
+        k = min(kmax, K - done)
+        Xs = rng.uniform(-1.0, 1.0, (A.n, k))
+        F = torch.from_numpy(np.ascontiguousarray((As @ Xs).T)).cuda()
+        X = torch.zeros_like(F)
+        rc, info = ddps.ddps_solve_many(S.h, F, X, tol)
+        solve_ms += info.t_solve_ms
+        G.record(F, X)
+        done += k
+        del F, X
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tr = G.train(epochs=epochs, batch_rows=batch_rows, lr=lr, time_budget_s=time_budget_s)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    stats = dict(K=K, pairs=G.rows, collect_s=t1 - t0, solve_ms_total=solve_ms, train_s=t2 - t1,
+                 epochs=tr["epochs"], loss_first_last=[tr["loss"][0], tr["loss"][-1]] if tr["loss"] else None)
+    if log:
+        log(f"learned guess: {G.rows} pairs from {K} right-hand sides in {t1 - t0:.1f} s, trained "
+            f"{tr['epochs']} epochs in {t2 - t1:.1f} s, loss {stats['loss_first_last']}")
+    return G, stats

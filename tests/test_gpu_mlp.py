@@ -305,3 +305,39 @@ def test_learned_guess_gain_on_time_sequence():
     assert np.median(rl) < 0.5 * np.median(rp)
     assert sum(r["learned"] for r in ev) >= 15
     assert il <= 1.05 * ip
+
+
+@pytest.mark.parametrize("retrieval", [0, 1])
+def test_learned_guess_in_every_application(retrieval):
+    """A network trained on plain solves of random right-hand sides
+    (guess.train_rhs_guess) and attached to the handle: every preconditioner
+    application picks its reduced-solve starting vector among 0, g^ and the
+    network's, so the solutions must still match the direct solve, and the
+    choices must add up to the reduced solves made."""
+    torch = torch_cuda()
+    from paper_1008_1700_amd import ddps, guess
+    d = configs.small_banded(6, [300, 340, 280, 330, 310, 290], 40, 21)
+    A = d["A"]
+    S = ddps.Solver(A, d["part_ptr"], dtype="bf16x3", inner_tol=1e-8, outer="refine", max_rhs=4,
+                    retrieval=retrieval)
+    try:
+        S.factor()
+        G, st = guess.train_rhs_guess(S, A, K=12, seed=3, tol=1e-11, hidden=64, epochs=30)
+        assert st["pairs"] == 12 * 5 and st["epochs"] == 30
+        assert st["loss_first_last"][1] < st["loss_first_last"][0]
+        rng = np.random.default_rng(5)
+        Xs = rng.uniform(-1, 1, (A.n, 4))
+        F = torch.from_numpy(np.ascontiguousarray((A.scipy() @ Xs).T)).cuda()
+        X = torch.zeros_like(F)
+        c0 = ddps.ddps_guess_counts(S.h)
+        G.attach(True)
+        rc, info = ddps.ddps_solve_many(S.h, F, X, 1e-11)
+        c1 = ddps.ddps_guess_counts(S.h)
+        G.attach(False)
+        assert rc == 0 and info.relres_inf <= 1e-11
+        assert relerr(host(X).T, Xs) <= 1e-8
+        made = sum(c1[q] - c0[q] for q in c1)
+        assert made == info.applications * 4
+        G.close()
+    finally:
+        S.close()

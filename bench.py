@@ -505,6 +505,10 @@ def copy_probe(gib=1.0):
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_1008_1700_amd", "tune_cache.json")
+# (mixed, FP64) reduced-solve tolerances: the fastest of a sweep on each
+# workload (C5: mixed 1e-4 1646 ms vs 1e-5 1715 ms vs 1e-6 1842 ms; FP64
+# 1e-5 4272 ms, 1e-6..1e-9 4309-4314 ms; C2: mixed 1e-6, FP64 1e-9)
+INNER_TOL = {"c5": (1e-4, 1e-5), "c2": (1e-6, 1e-9), "c3": (1e-6, 1e-9), "c1": (1e-6, 1e-9)}
 
 
 def main():
@@ -518,9 +522,10 @@ def main():
     ap.add_argument("--baseline-steps", type=int, default=3, help="timed steps of the plain FP64 run (at most --steps)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol", type=float, default=TOL)
-    # defaults: the fastest tolerance of a sweep for each mode on C2
-    ap.add_argument("--inner-tol", type=float, default=1e-6, help="reduced-solve tolerance, timed mode")
-    ap.add_argument("--inner-tol-f64", type=float, default=1e-9, help="reduced-solve tolerance, FP64 mode")
+    # defaults: the fastest reduced-solve tolerance of a sweep for each mode
+    # and workload (INNER_TOL)
+    ap.add_argument("--inner-tol", type=float, default=None, help="reduced-solve tolerance, timed mode")
+    ap.add_argument("--inner-tol-f64", type=float, default=None, help="reduced-solve tolerance, FP64 mode")
     ap.add_argument("--inner-prec", type=int, default=0,
                     help="inner BiCGStab preconditioner of the timed mode (0 none, 1 interface-local)")
     ap.add_argument("--graph-steps", type=int, default=0, help="extra steps timed with the factor graph")
@@ -542,6 +547,9 @@ def main():
     ap.add_argument("--c4-train", type=int, default=200)
     ap.add_argument("--c4-epochs", type=int, default=200)
     args = ap.parse_args()
+    it_mix, it_f64 = INNER_TOL.get(args.config, INNER_TOL["c2"])
+    args.inner_tol = it_mix if args.inner_tol is None else args.inner_tol
+    args.inner_tol_f64 = it_f64 if args.inner_tol_f64 is None else args.inner_tol_f64
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)

@@ -409,13 +409,18 @@ int ddps_residual_norms_noalloc(int64_t n, int32_t k, const int64_t* row_ptr, co
  * output for the input row [r_j / s_j, g^_j / q_j, 0, 0] (r = g^ - G^ g^,
  * s_j = max |r_j|, q_j = max |g^_j|; the layout of ddps_guess_features with
  * z^prev = g^).  A vector set with ddps_set_guess is not used meanwhile.
+ * After 8 reduced solves in a row in which the network's candidate was not
+ * the smallest, the network is retired: the reduced solves start from zero
+ * (the method's start) without trying candidates, until a network is
+ * attached again.
  * The network is used, not owned: keep it alive while attached.  Buffers for
  * the network's inputs and outputs are allocated here (not during solves).
  * Errors: DDPS_E_ARG (shape or stream mismatch), DDPS_E_NOMEM. */
 int ddps_set_guess_model(ddps_handle h, ddps_mlp net);
 
-/* Host int64[3]: reduced solves started so far from z0 = 0, from g^ and
- * from the network, over the handle's lifetime (with a network attached). */
+/* Host int64[4]: reduced solves started so far from z0 = 0, from g^ and
+ * from the network after trying the candidates, and those started without
+ * trying them (network retired), over the handle's lifetime. */
 int ddps_guess_counts(ddps_handle h, int64_t* counts);
 
 /* Device bytes held by the handle (host pointer). */

@@ -165,6 +165,8 @@ struct ddps_ctx {
   int gnet_din = 0;
   float *d_gX = nullptr, *d_gS = nullptr, *d_gY = nullptr;
   int64_t guess_counts[3] = {0, 0, 0};   // reduced solves started from 0, from g^, from the network
+  int gnet_losses = 0;                    // reduced solves in a row in which the network's candidate lost
+  int64_t gnet_skipped = 0;               // reduced solves started without trying (the network was retired)
   // last solve
   int last_k = 0;
   // timing
@@ -1203,6 +1205,7 @@ int learned_start(ddps_ctx* h, int k) {
     } else {
       ++h->guess_counts[2];
     }
+    h->gnet_losses = (nl[j] < ng[j] && nl[j] < nb[j]) ? 0 : h->gnet_losses + 1;
   }
   if (k < R) fill_f64(h->d_guess + (int64_t)k * m, m * (R - k), 0.0, s);
   HIPCHK(hipGetLastError());
@@ -1222,8 +1225,16 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
   if (rc) return rc;
   vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_gh, s);
   if (h->gnet && h->m > 0) {
-    if ((rc = learned_start(h, k))) return rc;
-    use_guess = 1;
+    // the network is retired (no candidates tried; the zero start of the
+    // method) once it has lost kRetire reduced solves in a row, until a
+    // network is attached again
+    constexpr int kRetire = 8;
+    if (h->gnet_losses < kRetire) {
+      if ((rc = learned_start(h, k))) return rc;
+      use_guess = 1;
+    } else {
+      h->gnet_skipped += k;
+    }
   }
   std::vector<int> st;
   rc = inner_solve(h, k, use_guess, inner_tol, h->opt.inner_maxit, iters, st);
@@ -1952,12 +1963,14 @@ int ddps_set_guess_model(ddps_handle h, ddps_mlp net) {
     h->gnet_din = din;
   }
   h->gnet = net;
+  h->gnet_losses = 0;
   return DDPS_OK;
 }
 
 int ddps_guess_counts(ddps_handle h, int64_t* counts) {
   if (!h || !counts) return DDPS_E_ARG;
   for (int q = 0; q < 3; ++q) counts[q] = h->guess_counts[q];
+  counts[3] = h->gnet_skipped;
   return DDPS_OK;
 }
 

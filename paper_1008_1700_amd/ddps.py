@@ -385,9 +385,9 @@ def ddps_set_guess_model(h, net):
 
 
 def ddps_guess_counts(h):
-    c = (_I64 * 3)()
+    c = (_I64 * 4)()
     _chk(lib().ddps_guess_counts(h, c), "ddps_guess_counts")
-    return dict(zero=c[0], ghat=c[1], learned=c[2])
+    return dict(zero=c[0], ghat=c[1], learned=c[2], retired=c[3])
 
 
 def ddps_memory(h):

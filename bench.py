@@ -63,7 +63,7 @@ def build_workload(name):
 
 def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_steps=None, exec_form=None,
              inner_prec=0, tune_cache=None, retrieval=0, tune_budget=60.0, learned=None, compare_steps=0,
-             backward_error_block=None, kappa=False):
+             backward_error_block=None, kappa=False, reduced="bicgstab"):
     """Set up one solver on the workload, tune its execution form, and time
     `steps` whole-path steps (refresh values, factor, solve) after `warmup`.
     learned: None, or dict(K, epochs, budget_s) -- the learned guess of a
@@ -75,7 +75,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
     fh = d["f"]
     k = 1 if fh.ndim == 1 else fh.shape[1]
     S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="refine", max_rhs=k,
-                    inner_prec=inner_prec, retrieval=retrieval)
+                    inner_prec=inner_prec, retrieval=retrieval, reduced=reduced)
     if k == 1:
         f = torch.from_numpy(np.ascontiguousarray(fh)).cuda()
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
@@ -83,7 +83,8 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         f = torch.from_numpy(np.ascontiguousarray(fh.T)).cuda()        # row j = right-hand side j
         x = torch.zeros(k, A.n, dtype=torch.float64, device="cuda")
     val = S.val
-    log(f"{mode}: setup done, n={A.n}, retrieval={retrieval}, {ddps.ddps_memory(S.h) / 1e9:.1f} GB")
+    log(f"{mode}: setup done, n={A.n}, retrieval={retrieval}, reduced={reduced}, "
+        f"{ddps.ddps_memory(S.h) / 1e9:.1f} GB")
     if exec_form is None:
         tune = ddps.ddps_autotune(S.h, tune_cache, tune_budget)   # execution form (stream groups, tiles), untimed
     else:
@@ -179,7 +180,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
     nf = np.linalg.norm(fh, np.inf, axis=0)
     xst = d["x_star"]
     out = dict(
-        mode=mode, retrieval=retrieval, rc=rc, ms_per_step=ms, rhs=k,
+        mode=mode, retrieval=retrieval, reduced=reduced, rc=rc, ms_per_step=ms, rhs=k,
         factor_ms=info.t_factor_ms, solve_ms=info.t_solve_ms,
         outer_iters=info.outer_iters, inner_iters_avg=info.inner_iters_avg,
         applications=info.applications,
@@ -455,7 +456,7 @@ def run_c4(args):
     kinds = configs.c4_kinds(A1, nx)
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
     S = ddps.Solver(A1, part, dtype=args.mode, inner_tol=itol, outer="refine", guess=True,
-                    inner_prec=args.inner_prec if args.mode != "f64" else 0)
+                    inner_prec=args.inner_prec if args.mode != "f64" else 0, reduced=args.reduced)
     tune = ddps.ddps_autotune(S.h, args.tune_cache, args.tune_budget)
     log(f"c4: n={A1.n} p={p} mode={args.mode} exec={tune}")
     t0 = time.perf_counter()
@@ -539,6 +540,8 @@ def main():
                          "do not fit (C3, C5)")
     ap.add_argument("--tune-budget", type=float, default=60.0, help="autotuner time budget per handle (s)")
     ap.add_argument("--no-learned", action="store_true", help="time the mixed solver without the learned guess")
+    ap.add_argument("--reduced", default="bicgstab", choices=["bicgstab", "direct"],
+                    help="reduced solve of the timed mode (the FP64 baseline keeps BiCGStab)")
     ap.add_argument("--guess-k", type=int, default=32, help="random right-hand sides the learned guess trains on")
     ap.add_argument("--guess-epochs", type=int, default=100)
     ap.add_argument("--guess-budget", type=float, default=30.0, help="training time budget (s)")
@@ -568,13 +571,14 @@ def main():
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
     iprec = args.inner_prec if args.mode != "f64" else 0
-    learned = None if (args.no_learned or args.mode == "f64" or len(d["part_ptr"]) < 3) else dict(
+    learned = None if (args.no_learned or args.mode == "f64" or args.reduced == "direct" or
+                       len(d["part_ptr"]) < 3) else dict(
         K=args.guess_k, epochs=args.guess_epochs, budget_s=args.guess_budget, seed=3)
     res = run_mode(d, args.mode, args.steps, args.warmup, args.tol, itol, graph_steps=args.graph_steps,
                    exec_form=exec_form, inner_prec=iprec, tune_cache=args.tune_cache,
                    retrieval=args.retrieval if args.mode != "f64" else max(args.retrieval_f64, 0),
                    tune_budget=args.tune_budget, learned=learned, compare_steps=args.compare_steps,
-                   backward_error_block=1 if len(d["part_ptr"]) > 2 else 0, kappa=True)
+                   backward_error_block=1 if len(d["part_ptr"]) > 2 else 0, kappa=True, reduced=args.reduced)
     log(f"{args.mode}: {json.dumps(res)}")
     base = None
     rf64 = args.retrieval_f64 if args.retrieval_f64 >= 0 else (1 if args.config in ("c3", "c5") else 0)

@@ -100,6 +100,13 @@ typedef struct {
                               0 = inf-norm (Section 4), 2 = 2-norm */
   int32_t work_slots;      /* retrieval 1: blocks whose spikes are computed at once (0 = as
                               many as the memory budget allows, at most p) */
+  int32_t reduced_solve;   /* step 6.3 of Figure 2: 0 = BiCGStab to inner_tol (Section 4);
+                              1 = solved directly (Section 3 allows either): block LU of G^
+                              over the interfaces, computed by ddps_factor (one t x t
+                              Schur complement factored per interface, a sequential chain),
+                              then a forward and a backward substitution per application.
+                              A zero pivot there is reported as DDPS_E_SINGULAR with
+                              bad_block = p and bad_row = the reduced row */
 } ddps_options;
 
 typedef struct {
@@ -119,7 +126,8 @@ typedef struct {
  * inner_maxit 1000, outer_maxit 1000, iterative refinement, zero guess,
  * max_rhs 1, no memory budget, null stream, automatic stream groups, no
  * graph, no inner preconditioner, spikes kept in full (retrieval 0),
- * inf-norm stopping test, automatic workspace slots. */
+ * inf-norm stopping test, automatic workspace slots, BiCGStab reduced
+ * solve. */
 void ddps_default_options(ddps_options* opt);
 
 /* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row
@@ -278,8 +286,9 @@ int ddps_autotune(ddps_handle h, const char* cache_path, double budget_s, int32_
  * ddps_timing_read reports launches, summed device milliseconds and
  * the algorithmic flops and bytes of those launches (host pointers), then
  * clears the counters.  kind: 0 = grouped GEMM (factor and spikes),
- * 1 = diagonal-tile LU, 2 = block-sweep GEMV, 3 = reduced-matrix product,
- * 4 = retrieval, 5 = CSR SpMV. */
+ * 1 = diagonal-tile LU, 2 = block-sweep GEMV, 3 = reduced-matrix product
+ * (and the direct reduced solve's substitutions), 4 = retrieval, 5 = CSR
+ * SpMV, 6 = the direct reduced solve's factorisation. */
 int ddps_timing_enable(ddps_handle h, int32_t kind, int32_t on);
 int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms, double* flops,
                      double* bytes);

@@ -36,8 +36,18 @@ using namespace ddps;
 
 namespace {
 
-enum LaunchKind { LK_GEMM = 0, LK_PANEL = 1, LK_GEMV = 2, LK_TIPMV = 3 };
-enum TimingKind { TK_GEMM = 0, TK_PANEL = 1, TK_SWEEP = 2, TK_RSPMV = 3, TK_RETR = 4, TK_CSR = 5, TK_N = 6 };
+enum LaunchKind { LK_GEMM = 0, LK_PANEL = 1, LK_GEMV = 2, LK_TIPMV = 3, LK_SUM = 4 };
+
+// A fixed-order sum of split-column partial products (LK_SUM launches).
+struct SumRec {
+  const double* parts;
+  int64_t pstride;
+  const double* yin;
+  double* yout;
+  int rows, ns, neg;
+};
+enum TimingKind { TK_GEMM = 0, TK_PANEL = 1, TK_SWEEP = 2, TK_RSPMV = 3, TK_RETR = 4, TK_CSR = 5, TK_RFAC = 6,
+                  TK_N = 7 };
 
 struct Launch {
   int kind;
@@ -97,6 +107,13 @@ struct ddps_ctx {
   int64_t nslots = 0, Nmax = 0;
   std::vector<int64_t> wslot;
   void* d_rhs = nullptr;     // p pairs of t x (t+1): left coupling (upper), right coupling (lower)
+  // Direct reduced solve (reduced_solve = 1): block LU of G^ over the p-1
+  // interfaces.  d_rP: P_j, d_rS: Sigma_j factored (inverse triangles), t x t
+  // each per interface; d_rW: work tiles T1, T2, Y0, Y1, an identity, and the
+  // two inversion work areas of the tile LU.
+  void *d_rP = nullptr, *d_rS = nullptr, *d_rW = nullptr;
+  std::vector<Launch> sch_rfac, sch_rsol;
+  std::vector<SumRec> sums;   // records of the LK_SUM launches
   void* d_tipcm = nullptr;   // 2(p-1) tip parts, t x 2t column-major (ld t), part 2i-1 / 2i as in d_tips
   int R = 1;
   // device data
@@ -229,6 +246,14 @@ struct ddps_ctx {
   }
   // column-major tip part q (t x 2t, leading dimension t)
   char* tipcm(int64_t q) const { return (char*)d_tipcm + (size_t)(q * 2 * t * (int64_t)t) * elt; }
+  // t x t spike tip of block i: its first t real rows (top) or last t rows,
+  // against the left (half 0) or right (half 1) coupling columns, with its
+  // leading dimension
+  std::pair<char*, int> tipv(int i, bool top, int half) const {
+    const BlockInfo& B = blk[i];
+    if (tips_only) return {tipcm(top ? 2 * i - 1 : 2 * i) + (size_t)half * t * t * elt, t};
+    return {spike(i, top ? B.pad : B.N - t, half ? t : 0), (int)B.N};
+  }
   char* sub(char* tile_base, int r, int c) const {  // element (r, c) of a t x t tile
     return tile_base + ((size_t)c * t + r) * elt;
   }
@@ -464,10 +489,125 @@ int fac_dtype_code(int d) {
   }
 }
 
+// One t x t tile of a schedule's tile LU: its storage (leading dimension t),
+// two work areas of t x (t/2 + 64) for the inversion products, and the
+// block, global row and padded-layout row (pivot threshold index) of its
+// first row for the singular-pivot report.
+struct TileLu {
+  char* D;
+  char* w4;
+  char* w5;
+  int block;
+  int64_t row0, vrow0;
+};
+
+// Unpivoted LU of every tile of `items` in place, batched over the tiles,
+// then the inverses of both triangles: on exit a tile holds L^{-1} strictly
+// below the diagonal (unit diagonal implied) and U^{-1} on and above it.
+void build_tile_lu(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<TileLu>& items, std::vector<Launch>& S) {
+  const int t = h->t, Q = t / 64;
+  // LU in 64-column panels (panel LU with the inverses of its 64 x 64
+  // triangles, then column and row panels), blocked in two levels: inside
+  // an outer panel of kOuter columns [J0, J1) each 64-column step updates
+  // only the rows of the outer panel (all columns to its right) and the
+  // columns of the outer panel (all rows below); the rest of the trailing
+  // matrix, rows and columns >= J1, takes the sum of those steps' products
+  // as one rank-(J1 - J0) update after the outer panel.  Same products as a
+  // rank-64 update per step, grouped so that the trailing matrix is read
+  // and written once per outer panel instead of once per step.
+  constexpr int kOuter = 256;
+  for (int J0 = 0; J0 < t; J0 += kOuter) {
+    const int J1 = std::min(t, J0 + kOuter);
+    for (int j64 = J0; j64 < J1; j64 += 64) {
+      const int rest = t - j64 - 64, w = J1 - j64 - 64;
+      sb.begin(LK_PANEL);
+      for (const TileLu& it : items) sb.add_panel(h->sub(it.D, j64, j64), t, it.block, it.row0 + j64, it.vrow0 + j64);
+      sb.end(S);
+      if (rest <= 0) continue;
+      sb.begin(LK_GEMM);
+      for (const TileLu& it : items) {
+        char* D = it.D;
+        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
+                    rest, 64, 64, G_B_MUP | G_B_UP);
+        sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
+                    64, rest, 64, G_A_MLU | G_A_LO);
+      }
+      sb.end(S);
+      if (w <= 0) continue;
+      sb.begin(LK_GEMM);
+      for (const TileLu& it : items) {
+        char* D = it.D;
+        // rows of the outer panel below this step, every column to the right
+        sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
+                    h->sub(D, j64 + 64, j64 + 64), t, w, rest, 64, G_NEG);
+        // rows below the outer panel, columns of the outer panel
+        if (t > J1)
+          sb.add_gemm(h->sub(D, J1, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, J1, j64 + 64), t,
+                      h->sub(D, J1, j64 + 64), t, t - J1, w, 64, G_NEG);
+      }
+      sb.end(S);
+    }
+    if (t > J1) {
+      sb.begin(LK_GEMM);
+      for (const TileLu& it : items) {
+        char* D = it.D;
+        sb.add_gemm(h->sub(D, J1, J0), t, h->sub(D, J0, J1), t, h->sub(D, J1, J1), t, h->sub(D, J1, J1), t, t - J1,
+                    t - J1, J1 - J0, G_NEG);
+      }
+      sb.end(S);
+    }
+  }
+  // inverse triangles of the whole tile by recursive halving of the panel
+  // range: for a split [lo, mid) | [mid, hi) whose halves are inverted,
+  //   X10 = -X11 (L10 X00),   Y01 = -(Y00 U01) Y11
+  // (X = L^{-1}, Y = U^{-1}); all splits of one depth, over all blocks,
+  // share a launch pair.
+  {
+    std::vector<std::vector<std::array<int, 3>>> levels;
+    std::function<void(int, int, int)> rec = [&](int lo, int hi, int d) {
+      if (hi - lo <= 1) return;
+      const int mid = (lo + hi) / 2;
+      if ((int)levels.size() <= d) levels.resize(d + 1);
+      levels[d].push_back({lo, mid, hi});
+      rec(lo, mid, d + 1);
+      rec(mid, hi, d + 1);
+    };
+    rec(0, Q, 0);
+    for (int d = (int)levels.size() - 1; d >= 0; --d) {
+      sb.begin(LK_GEMM);
+      for (const TileLu& it : items) {
+        char* D = it.D;
+        for (auto& c : levels[d]) {
+          const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
+          const int m0 = mid - lo, m1 = hi - mid;
+          sb.add_gemm(h->sub(D, mid, lo), t, h->sub(D, lo, lo), t, nullptr, 0, it.w4 + (size_t)mid * h->elt, t,
+                      m1, m0, m0, G_B_MLU | G_B_LO);
+          sb.add_gemm(h->sub(D, lo, lo), t, h->sub(D, lo, mid), t, nullptr, 0, it.w5 + (size_t)lo * h->elt, t,
+                      m0, m1, m0, G_A_MUP | G_A_UP);
+        }
+      }
+      sb.end(S);
+      sb.begin(LK_GEMM);
+      for (const TileLu& it : items) {
+        char* D = it.D;
+        for (auto& c : levels[d]) {
+          const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
+          const int m0 = mid - lo, m1 = hi - mid;
+          sb.add_gemm(h->sub(D, mid, mid), t, it.w4 + (size_t)mid * h->elt, t, nullptr, 0, h->sub(D, mid, lo), t,
+                      m1, m0, m1, G_NEG | G_A_MLU | G_A_LO);
+          sb.add_gemm(it.w5 + (size_t)lo * h->elt, t, h->sub(D, mid, mid), t, nullptr, 0, h->sub(D, lo, mid), t,
+                      m0, m1, m1, G_NEG | G_B_MUP | G_B_UP);
+        }
+      }
+      sb.end(S);
+    }
+  }
+}
+
 // Factor schedule of the blocks in `members` (ascending), appended to S.
 void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<int>& members,
                            std::vector<Launch>& S) {
-  const int t = h->t, p = h->p, Q = t / 64;
+  const int t = h->t, p = h->p;
   int Tmax = 0;
   for (int i : members) Tmax = std::max<int>(Tmax, (int)h->blk[i].T);
   for (int k = 0; k < Tmax; ++k) {
@@ -498,105 +638,14 @@ void build_factor_schedule(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<i
       if (k == B.T - 1 && i < p - 1) sb.add_copy(h->spike(i, (int64_t)k * t, t), N, h->scr(i, 3), t, t, t);
     }
     sb.end(S);
-    // LU of S_k in 64-column panels (panel LU with the inverses of its 64 x 64
-    // triangles, then column and row panels), blocked in two levels: inside
-    // an outer panel of kOuter columns [J0, J1) each 64-column step updates
-    // only the rows of the outer panel (all columns to its right) and the
-    // columns of the outer panel (all rows below); the rest of the trailing
-    // matrix, rows and columns >= J1, takes the sum of those steps' products
-    // as one rank-(J1 - J0) update after the outer panel.  Same products as a
-    // rank-64 update per step, grouped so that the trailing matrix is read
-    // and written once per outer panel instead of once per step.
-    constexpr int kOuter = 256;
-    for (int J0 = 0; J0 < t; J0 += kOuter) {
-      const int J1 = std::min(t, J0 + kOuter);
-      for (int j64 = J0; j64 < J1; j64 += 64) {
-        const int rest = t - j64 - 64, w = J1 - j64 - 64;
-        sb.begin(LK_PANEL);
-        for (int i : act) {
-          const BlockInfo& B = h->blk[i];
-          sb.add_panel(h->sub(h->tile(i, 0, k), j64, j64), t, i, B.s - B.pad + (int64_t)k * t + j64,
-                       B.voff + (int64_t)k * t + j64);
-        }
-        sb.end(S);
-        if (rest <= 0) continue;
-        sb.begin(LK_GEMM);
-        for (int i : act) {
-          char* D = h->tile(i, 0, k);
-          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64), t, nullptr, 0, h->sub(D, j64 + 64, j64), t,
-                      rest, 64, 64, G_B_MUP | G_B_UP);
-          sb.add_gemm(h->sub(D, j64, j64), t, h->sub(D, j64, j64 + 64), t, nullptr, 0, h->sub(D, j64, j64 + 64), t,
-                      64, rest, 64, G_A_MLU | G_A_LO);
-        }
-        sb.end(S);
-        if (w <= 0) continue;
-        sb.begin(LK_GEMM);
-        for (int i : act) {
-          char* D = h->tile(i, 0, k);
-          // rows of the outer panel below this step, every column to the right
-          sb.add_gemm(h->sub(D, j64 + 64, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, j64 + 64, j64 + 64), t,
-                      h->sub(D, j64 + 64, j64 + 64), t, w, rest, 64, G_NEG);
-          // rows below the outer panel, columns of the outer panel
-          if (t > J1)
-            sb.add_gemm(h->sub(D, J1, j64), t, h->sub(D, j64, j64 + 64), t, h->sub(D, J1, j64 + 64), t,
-                        h->sub(D, J1, j64 + 64), t, t - J1, w, 64, G_NEG);
-        }
-        sb.end(S);
-      }
-      if (t > J1) {
-        sb.begin(LK_GEMM);
-        for (int i : act) {
-          char* D = h->tile(i, 0, k);
-          sb.add_gemm(h->sub(D, J1, J0), t, h->sub(D, J0, J1), t, h->sub(D, J1, J1), t, h->sub(D, J1, J1), t, t - J1,
-                      t - J1, J1 - J0, G_NEG);
-        }
-        sb.end(S);
-      }
-    }
-    // inverse triangles of the whole tile by recursive halving of the panel
-    // range: for a split [lo, mid) | [mid, hi) whose halves are inverted,
-    //   X10 = -X11 (L10 X00),   Y01 = -(Y00 U01) Y11
-    // (X = L^{-1}, Y = U^{-1}); all splits of one depth, over all blocks,
-    // share a launch pair.
     {
-      std::vector<std::vector<std::array<int, 3>>> levels;
-      std::function<void(int, int, int)> rec = [&](int lo, int hi, int d) {
-        if (hi - lo <= 1) return;
-        const int mid = (lo + hi) / 2;
-        if ((int)levels.size() <= d) levels.resize(d + 1);
-        levels[d].push_back({lo, mid, hi});
-        rec(lo, mid, d + 1);
-        rec(mid, hi, d + 1);
-      };
-      rec(0, Q, 0);
-      for (int d = (int)levels.size() - 1; d >= 0; --d) {
-        sb.begin(LK_GEMM);
-        for (int i : act) {
-          char* D = h->tile(i, 0, k);
-          for (auto& c : levels[d]) {
-            const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
-            const int m0 = mid - lo, m1 = hi - mid;
-            sb.add_gemm(h->sub(D, mid, lo), t, h->sub(D, lo, lo), t, nullptr, 0, h->scr(i, 4) + (size_t)mid * h->elt, t,
-                        m1, m0, m0, G_B_MLU | G_B_LO);
-            sb.add_gemm(h->sub(D, lo, lo), t, h->sub(D, lo, mid), t, nullptr, 0, h->scr(i, 5) + (size_t)lo * h->elt, t,
-                        m0, m1, m0, G_A_MUP | G_A_UP);
-          }
-        }
-        sb.end(S);
-        sb.begin(LK_GEMM);
-        for (int i : act) {
-          char* D = h->tile(i, 0, k);
-          for (auto& c : levels[d]) {
-            const int lo = c[0] * 64, mid = c[1] * 64, hi = c[2] * 64;
-            const int m0 = mid - lo, m1 = hi - mid;
-            sb.add_gemm(h->sub(D, mid, mid), t, h->scr(i, 4) + (size_t)mid * h->elt, t, nullptr, 0, h->sub(D, mid, lo), t,
-                        m1, m0, m1, G_NEG | G_A_MLU | G_A_LO);
-            sb.add_gemm(h->scr(i, 5) + (size_t)lo * h->elt, t, h->sub(D, mid, mid), t, nullptr, 0, h->sub(D, lo, mid), t,
-                        m0, m1, m1, G_NEG | G_B_MUP | G_B_UP);
-          }
-        }
-        sb.end(S);
+      std::vector<TileLu> items;
+      for (int i : act) {
+        const BlockInfo& B = h->blk[i];
+        items.push_back({h->tile(i, 0, k), h->scr(i, 4), h->scr(i, 5), i, B.s - B.pad + (int64_t)k * t,
+                         B.voff + (int64_t)k * t});
       }
+      build_tile_lu(h, sb, items, S);
     }
     // post(k): off-diagonal factors and forward spike sweep
     sb.begin(LK_GEMM);
@@ -700,6 +749,122 @@ void build_batch_tips(ddps_ctx* h, ScheduleBuilder& sb, const std::vector<int>& 
     if (i < p - 1) sb.add_copy(h->spike(i, B.N - t, 0), (int)B.N, h->tipcm(2 * i), t, t, 2 * t);
   }
   sb.end(S);
+}
+
+// Direct solve of the reduced system (Figure 2, step 6.3 solved "directly").
+// In the interface ordering (interface j = the last t rows of block j, a_j,
+// then the first t rows of block j+1, b_j) G^ is block tridiagonal with
+// 2t x 2t blocks: D_j = [[I, V_j^bot], [W_{j+1}^top, I]], the coupling of
+// a_j to a_{j-1} is W_j^bot and that of b_j to b_{j+1} is V_{j+1}^top (W, V:
+// the left and right spikes, ^top / ^bot their first / last t rows).  Block
+// LU without pivoting then keeps the identity diagonal blocks:
+//   S_j = [[I, P_j], [Q_j, I]],  Q_j = W_{j+1}^top,
+//   P_0 = V_0^bot,  P_j = V_j^bot - W_j^bot Y_{j-1} V_j^top,
+//   Y_j = -Sigma_j^{-1} P_j (the top-right block of S_j^{-1}),
+//   Sigma_j = I - P_j Q_j,
+// so each interface factors one t x t matrix Sigma_j (unpivoted, inverse
+// triangles), a sequential chain over the interfaces.  Its forward and
+// backward substitutions apply S_j^{-1}[u; v] = [x1; v - Q_j x1] with
+// x1 = Sigma_j^{-1}(u - P_j v).  The tips are used unmasked: columns of G
+// outside c are zero, so the solution on c is that of the masked system, and
+// the entries outside c are zeroed afterwards.
+void build_reduced_direct(ddps_ctx* h, ScheduleBuilder& sb) {
+  h->sch_rfac.clear();
+  h->sch_rsol.clear();
+  h->sums.clear();
+  if (!h->d_rP || h->p < 2) return;
+  const int t = h->t, M = h->p - 1;
+  const size_t tt = (size_t)t * t * h->elt;
+  auto rP = [&](int j) { return (char*)h->d_rP + (size_t)j * tt; };
+  auto rS = [&](int j) { return (char*)h->d_rS + (size_t)j * tt; };
+  char* W = (char*)h->d_rW;
+  char *T1 = W, *T2 = W + tt, *Y[2] = {W + 2 * tt, W + 3 * tt}, *I = W + 4 * tt, *w4 = W + 5 * tt;
+  char* w5 = w4 + (size_t)t * (t / 2 + 64) * h->elt;
+  // these launches hold one t x t problem each: 64 x 64 tiles fill the GPU
+  // best; they leave the factor schedule's per-launch tile choices (read by
+  // launch index) alone
+  const int pol = h->tile_policy, cur = h->mode_cursor;
+  h->tile_policy = 1;
+  for (int j = 0; j < M; ++j) {
+    auto Vb = h->tipv(j, false, 1), Wb = h->tipv(j, false, 0), Q = h->tipv(j + 1, true, 0);
+    sb.begin(LK_GEMM);
+    if (j == 0) {
+      sb.add_copy(Vb.first, Vb.second, rP(0), t, t, t);
+    } else {
+      auto Vt = h->tipv(j, true, 1);
+      sb.add_gemm(Y[(j - 1) & 1], t, Vt.first, Vt.second, nullptr, 0, T1, t, t, t, t, 0);
+      sb.end(h->sch_rfac);
+      sb.begin(LK_GEMM);
+      sb.add_gemm(Wb.first, Wb.second, T1, t, Vb.first, Vb.second, rP(j), t, t, t, t, G_NEG);
+    }
+    sb.end(h->sch_rfac);
+    sb.begin(LK_GEMM);
+    sb.add_gemm(rP(j), t, Q.first, Q.second, I, t, rS(j), t, t, t, t, G_NEG);
+    sb.end(h->sch_rfac);
+    build_tile_lu(h, sb, {TileLu{rS(j), w4, w5, h->p, (int64_t)j * 2 * t, h->Np}}, h->sch_rfac);
+    if (j < M - 1) {
+      sb.begin(LK_GEMM);
+      sb.add_gemm(rS(j), t, rP(j), t, nullptr, 0, T2, t, t, t, t, G_A_MLU | G_A_LO);
+      sb.end(h->sch_rfac);
+      sb.begin(LK_GEMM);
+      sb.add_gemm(rS(j), t, T2, t, nullptr, 0, Y[j & 1], t, t, t, t, G_NEG | G_A_MUP | G_A_UP);
+      sb.end(h->sch_rfac);
+    }
+  }
+  h->tile_policy = pol;
+  h->mode_cursor = cur;
+  // substitutions on d_zh (holding g^ on entry), with temporaries in d_r,
+  // d_p.  Each t x t product is one launch of `ns` column ranges (partial
+  // products in d_tv, part q at offset q t) and one fixed-order sum: a single
+  // t x t product has only t/64 row slabs, too few to keep the GPU's loads
+  // in flight.
+  const double eb = (double)h->elt;
+  double* z = h->d_zh;
+  double* tmp = h->d_r;
+  double* tmp2 = h->d_p;
+  double* parts = h->d_tv;
+  const int ns = std::max(1, std::min<int>({8, 2 * M, t / 64}));
+  auto vec = [&](int j, int half) { return z + (int64_t)(2 * j + half) * t; };
+  auto gemv = [&](const char* A, int lda, const double* x, const double* yin, double* yout, int flags, int tri) {
+    sb.begin(LK_GEMV);
+    for (int q = 0; q < ns; ++q) {
+      GemvProb G{};
+      G.A = A;
+      G.lda = lda;
+      G.x1 = x;
+      G.x2 = x;
+      G.split = t;
+      G.rows = t;
+      G.cb = (int)((int64_t)t * q / ns);
+      G.ce = (int)((int64_t)t * (q + 1) / ns);
+      G.yout = parts + (int64_t)q * t;
+      G.flags = flags & (V_A_MLU | V_A_MUP | V_A_MLO);
+      G.tri = tri;
+      sb.add_gemv(G, eb);
+    }
+    sb.end(h->sch_rsol);
+    h->sums.push_back(SumRec{parts, t, yin, yout, t, ns, (flags & V_NEG) ? 1 : 0});
+    h->sch_rsol.push_back(Launch{LK_SUM, (int64_t)h->sums.size() - 1, 1, (t + 255) / 256, 0.0, 0.0, 0, -1});
+  };
+  for (int j = 1; j < M; ++j) {
+    // w_j(a) -= W_j^bot x1, x1 = Sigma_{j-1}^{-1}(u_{j-1} - P_{j-1} v_{j-1})
+    gemv(rP(j - 1), t, vec(j - 1, 1), vec(j - 1, 0), tmp, V_NEG, 0);
+    gemv(rS(j - 1), t, tmp, nullptr, tmp2, V_A_MLU, 1);
+    gemv(rS(j - 1), t, tmp2, nullptr, tmp, V_A_MUP, 2);
+    auto Wb = h->tipv(j, false, 0);
+    gemv(Wb.first, Wb.second, tmp, vec(j, 0), vec(j, 0), V_NEG, 0);
+  }
+  for (int j = M - 1; j >= 0; --j) {
+    if (j < M - 1) {
+      auto Vt = h->tipv(j + 1, true, 1);
+      gemv(Vt.first, Vt.second, vec(j + 1, 1), vec(j, 1), vec(j, 1), V_NEG, 0);
+    }
+    gemv(rP(j), t, vec(j, 1), vec(j, 0), tmp, V_NEG, 0);
+    gemv(rS(j), t, tmp, nullptr, tmp2, V_A_MLU, 1);
+    gemv(rS(j), t, tmp2, nullptr, vec(j, 0), V_A_MUP, 2);
+    auto Q = h->tipv(j + 1, true, 0);
+    gemv(Q.first, Q.second, vec(j, 0), vec(j, 1), vec(j, 1), V_NEG, 0);
+  }
 }
 
 void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
@@ -880,6 +1045,11 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
       launch_gemm(h->gdt, L.mode, h->d_gemm + L.off, L.nprob, L.nwg, s, L.ord >= 0 ? h->d_order + L.ord : nullptr);
       break;
     case LK_PANEL: launch_panel(h->sdt, h->d_panel + L.off, L.nprob, h->d_thresh, h->d_bad, s); break;
+    case LK_SUM: {
+      const SumRec& q = h->sums[L.off];
+      sum_parts(q.rows, R, q.ns, q.parts, q.pstride, ldy, q.yin, q.yout, q.neg, s);
+      break;
+    }
     case LK_TIPMV:
       launch_tipmv(h->sdt, R, h->tip_nseg, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
       break;
@@ -936,9 +1106,9 @@ int do_scatter(ddps_ctx* h, hipStream_t s) {
 }
 
 int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, int64_t ldy, int tk_gemv,
-                 hipStream_t s) {
+                 hipStream_t s, int tk_all = -1) {
   for (const Launch& L : S) {
-    const int tk = L.kind == LK_GEMM ? TK_GEMM : L.kind == LK_PANEL ? TK_PANEL : tk_gemv;
+    const int tk = tk_all >= 0 ? tk_all : L.kind == LK_GEMM ? TK_GEMM : L.kind == LK_PANEL ? TK_PANEL : tk_gemv;
     run_launch(h, L, R, ldx, ldy, nullptr, nullptr, nullptr, tk, s);
   }
   HIPCHK(hipGetLastError());
@@ -964,6 +1134,7 @@ int enqueue_factor(ddps_ctx* h) {
     for (int g = 0; g < G; ++g)
       if ((rc = run_schedule(h, h->sch_group[g], 1, 0, 0, TK_GEMM, f))) return rc;
     if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
+    if ((rc = run_schedule(h, h->sch_rfac, 1, 0, 0, TK_GEMM, f, TK_RFAC))) return rc;
     HIPCHK(hipGetLastError());
     return DDPS_OK;
   }
@@ -976,6 +1147,7 @@ int enqueue_factor(ddps_ctx* h) {
   }
   for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(f, h->gevent[g - 1], 0));
   if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
+  if ((rc = run_schedule(h, h->sch_rfac, 1, 0, 0, TK_GEMM, f, TK_RFAC))) return rc;
   HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
@@ -1040,6 +1212,7 @@ int build_schedules(ddps_ctx* h) {
   h->sch_bwd.clear();
   h->sch_retr.clear();
   build_solve_schedules(h, sb);
+  build_reduced_direct(h, sb);
   h->free_ptr(h->d_gemm);
   h->free_ptr(h->d_order);
   h->free_ptr(h->d_panel);
@@ -1086,6 +1259,15 @@ int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::v
   iters.assign(k, 0);
   status_out.assign(k, KS_CONVERGED);
   if (m == 0) {
+    return DDPS_OK;
+  }
+  if (!h->sch_rsol.empty()) {
+    // direct: block LU substitutions over the interfaces (no iterations)
+    HIPCHK(hipMemcpyAsync(h->d_zh, h->d_gh, sizeof(double) * m * R, hipMemcpyDeviceToDevice, s));
+    int rc = run_schedule(h, h->sch_rsol, R, m, m, TK_RSPMV);
+    if (rc) return rc;
+    vec_apply_mask(m, R, h->d_mask, h->d_zh, s);
+    HIPCHK(hipGetLastError());
     return DDPS_OK;
   }
   const int W2 = vec_grid(m);
@@ -1224,7 +1406,7 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
   rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
   if (rc) return rc;
   vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_gh, s);
-  if (h->gnet && h->m > 0) {
+  if (h->gnet && h->m > 0 && h->sch_rsol.empty()) {
     // the network is retired (no candidates tried; the zero start of the
     // method) once it has lost kRetire reduced solves in a row, until a
     // network is attached again
@@ -1353,6 +1535,7 @@ void ddps_default_options(ddps_options* o) {
   o->retrieval = 0;
   o->norm = 0;
   o->work_slots = 0;
+  o->reduced_solve = 0;
 }
 
 const char* ddps_status_string(int s) {
@@ -1418,7 +1601,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   const ddps_options& o = h->opt;
   if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
       o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
-      o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0) {
+      o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0 ||
+      o.reduced_solve < 0 || o.reduced_solve > 1) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1510,6 +1694,9 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   h->tip_nseg = (R <= 2 && p > 1 && !h->tips_only) ? tipmv_segments(h->sdt, t) : 0;
   if (h->tip_nseg > 0 || h->tips_only) need += (size_t)m * 2 * t * h->elt;
   if (h->tips_only) need += (size_t)p * h->pair_elems() * h->elt;
+  const bool direct = o.reduced_solve == 1 && p > 1;
+  const size_t rw_elems = 5 * (size_t)t * t + 2 * (size_t)t * (t / 2 + 64);
+  if (direct) need += (2 * (size_t)(p - 1) * t * t + rw_elems) * h->elt;
   need += (size_t)p * 2 * t * 8 + (size_t)m * (8 + 8 + 8);
   need += (size_t)h->Np * R * 8 * 2 + (size_t)h->Np * 8;
   need += (size_t)m * R * 8 * 11;
@@ -1574,10 +1761,30 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   }
   if ((rc = h->alloc_raw(vp, (size_t)h->nslots * h->scr_per_block * h->elt))) return fail(rc);
   h->d_scratch = vp;
+  if (direct) {
+    if ((rc = h->alloc_raw(vp, (size_t)(p - 1) * t * t * h->elt))) return fail(rc);
+    h->d_rP = vp;
+    if ((rc = h->alloc_raw(vp, (size_t)(p - 1) * t * t * h->elt))) return fail(rc);
+    h->d_rS = vp;
+    if ((rc = h->alloc_raw(vp, rw_elems * h->elt))) return fail(rc);
+    h->d_rW = vp;
+    // the identity tile (fifth work tile), built on the host once
+    if (h->sdt == 0) {
+      std::vector<double> id((size_t)t * t, 0.0);
+      for (int i = 0; i < t; ++i) id[(size_t)i * t + i] = 1.0;
+      if (hipMemcpy((char*)vp + 4 * (size_t)t * t * 8, id.data(), id.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DDPS_E_HIP);
+    } else {
+      std::vector<float> id((size_t)t * t, 0.f);
+      for (int i = 0; i < t; ++i) id[(size_t)i * t + i] = 1.f;
+      if (hipMemcpy((char*)vp + 4 * (size_t)t * t * 4, id.data(), id.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DDPS_E_HIP);
+    }
+  }
   if ((rc = h->alloc(h->d_colnorm, (int64_t)p * 2 * t)) || (rc = h->alloc(h->d_mask, std::max<int64_t>(m, 1))) ||
       (rc = h->alloc(h->d_c, std::max<int64_t>(m, 1))) || (rc = h->alloc(h->d_rrow, std::max<int64_t>(m, 1))) ||
       (rc = h->alloc(h->d_blk, p)) || (rc = h->alloc(h->d_ypad, h->Np * R)) || (rc = h->alloc(h->d_vpad, h->Np * R)) ||
-      (rc = h->alloc(h->d_thresh, h->Np)))
+      (rc = h->alloc(h->d_thresh, h->Np + t)))
     return fail(rc);
   const int64_t mR = std::max<int64_t>(m, 1) * R;
   if ((rc = h->alloc(h->d_gh, mR)) || (rc = h->alloc(h->d_zh, mR)) || (rc = h->alloc(h->d_r, mR)) ||
@@ -1621,6 +1828,9 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (hipMemcpyAsync(h->d_blk, h->blk.data(), sizeof(BlockInfo) * p, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(DDPS_E_HIP);
   const double eps = h->sdt == 0 ? 2.220446049250313e-16 : 1.1920928955078125e-7;
+  // the t entries after the padded rows stay 0: pivot thresholds of the
+  // reduced system's tile LU (only a zero or non-finite pivot is reported)
+  fill_f64(h->d_thresh + h->Np, t, 0.0, s);
   setup_row_thresh(n, p, h->Np, h->d_part, h->d_blk, h->d_rowptr, h->d_col, h->d_val, eps, h->d_thresh, s);
   // execution resources and schedules
   if (hipStreamCreateWithFlags(&h->fstream, hipStreamNonBlocking) != hipSuccess ||

@@ -223,6 +223,10 @@ void residual_norms_cols(int64_t n, int k, const int64_t* row_ptr, const int32_t
 void coupling_rhs(int64_t Np, int R, int k, int p, int t, const BlockInfo* blocks, const int64_t* row_ptr,
                   const int32_t* col, const double* val, const double* y, int64_t ldy, const double* zh, int64_t m,
                   const double* mask, double* yp, hipStream_t s);
+// yout = yin -/+ sum of ns partial vectors (fixed order), rows x R, column
+// stride ld, part q at parts + q * pstride; yin may be null, may alias yout
+void sum_parts(int rows, int R, int ns, const double* parts, int64_t pstride, int64_t ld, const double* yin,
+               double* yout, int neg, hipStream_t s);
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s);
 void dot2(int R, int64_t n, const double* a0, const double* b0, const double* a1, const double* b1,

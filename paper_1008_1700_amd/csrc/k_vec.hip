@@ -489,6 +489,22 @@ __global__ __launch_bounds__(256) void k_coupling_rhs(int64_t Np, int p, int t, 
   }
 }
 
+// yout = yin -/+ (parts[0] + ... + parts[ns-1]) over `rows` entries of R
+// columns (column stride ld; part s at parts + s * pstride), summed in that
+// fixed order: the split-column products of the direct reduced solve.
+__global__ __launch_bounds__(256) void k_sum_parts(int rows, int R, int ns, const double* __restrict__ parts,
+                                                   int64_t pstride, int64_t ld, const double* yin, double* yout,
+                                                   int neg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  for (int j = 0; j < R; ++j) {
+    double acc = 0.0;
+    for (int q = 0; q < ns; ++q) acc += parts[q * pstride + i + j * ld];
+    const double base = yin ? yin[i + j * ld] : 0.0;
+    yout[i + j * ld] = neg ? base - acc : base + acc;
+  }
+}
+
 // Reduce [W][R][4] residual partials to out[R][4] (max, sum, max, sum).
 template <int R>
 __global__ void k_resid_reduce(int W, const double* __restrict__ part, double* __restrict__ out) {
@@ -644,6 +660,11 @@ void coupling_rhs(int64_t Np, int R, int k, int p, int t, const BlockInfo* block
                   const double* mask, double* yp, hipStream_t s) {
   DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_coupling_rhs<RR>, dim3(grid_for(Np)), dim3(256), 0, s, Np, p, t, k, blocks,
                                         row_ptr, col, val, y, ldy, zh, m, mask, yp));
+}
+void sum_parts(int rows, int R, int ns, const double* parts, int64_t pstride, int64_t ld, const double* yin,
+               double* yout, int neg, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3((rows + 255) / 256), dim3(256), 0, s, rows, R, ns, parts, pstride, ld, yin,
+                     yout, neg);
 }
 void lincomb(int R, int64_t n, const Coef3& cf, const double* X, const double* Y, const double* Z,
              double* out, hipStream_t s) {

@@ -19,7 +19,7 @@ F64, F32, BF16X3, BF16 = 0, 1, 2, 3
 DTYPES = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16": BF16}
 STATUS = {0: "DDPS_OK", -1: "DDPS_E_ARG", -2: "DDPS_E_NOMEM", -3: "DDPS_E_NOCONV", -4: "DDPS_E_SINGULAR",
           -5: "DDPS_E_BREAKDOWN", -6: "DDPS_E_STATE", -7: "DDPS_E_HIP"}
-TIMING_KINDS = {"gemm": 0, "panel": 1, "sweep": 2, "reduced": 3, "retrieval": 4, "csr": 5}
+TIMING_KINDS = {"gemm": 0, "panel": 1, "sweep": 2, "reduced": 3, "retrieval": 4, "csr": 5, "reduced_factor": 6}
 
 
 class DDPSError(RuntimeError):
@@ -48,6 +48,7 @@ class ddps_options(ctypes.Structure):
         ("retrieval", ctypes.c_int32),
         ("norm", ctypes.c_int32),
         ("work_slots", ctypes.c_int32),
+        ("reduced_solve", ctypes.c_int32),
     ]
 
 
@@ -411,7 +412,8 @@ class Solver:
 
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
-                 mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0):
+                 mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0,
+                 reduced="bicgstab"):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -431,6 +433,7 @@ class Solver:
         o.retrieval = int(retrieval)
         o.norm = int(norm)
         o.work_slots = int(work_slots)
+        o.reduced_solve = 1 if reduced == "direct" else 0
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

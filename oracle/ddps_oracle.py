@@ -433,6 +433,17 @@ def solve(n, row_ptr, col, val, part_ptr, f, delta=0.0, tol=1e-10, outer="refine
     return x, info, P
 
 
+def direct_solve(A, f):
+    """x = A^{-1} f by sparse LU with partial pivoting (SuperLU through
+    scipy): the exact solution that every DDPS solve approaches (Section 3:
+    with exact blocks and an exact reduced solve the method is a direct
+    solver), for systems too large for the dense routines.  f may hold
+    several columns."""
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(sp.csc_matrix(A))
+    return lu.solve(np.asarray(f, dtype=np.float64))
+
+
 def hager_higham_cond1(solve, solveT, n, A1norm, iters=5):
     """Estimate of kappa_1(A) = ||A||_1 ||A^{-1}||_1 (Hager 1984; Higham 1988,
     Algorithm 2.1): a power-method style search for the column of A^{-1}

@@ -73,3 +73,26 @@ def test_c2_mixed_precision_solve(c2, dtype):
         assert relerr(xs, c2["x_star"]) <= 1e-8
     finally:
         S.close()
+
+
+# bounds on the normwise backward error of the factors: a small multiple of
+# the unit roundoff of the products (FP64 2^-53, FP32 and split bf16 2^-24,
+# bf16 2^-9) times the growth over the band LU's tile steps
+BACKWARD_BOUND = {"f64": 1e-13, "f32": 1e-5, "bf16x3": 1e-5, "bf16": 3e-2}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16x3", "bf16"])
+def test_c2_factor_backward_error(c2, dtype):
+    """||A_ii - L~ U~||_F / ||A_ii||_F for block 1 (an interior block: t =
+    1024, 8 tiles) from the GPU's factor tiles, per precision.  The FP64
+    factors pin the measurement itself at roundoff level."""
+    from bench import factor_backward_error
+    S = make_solver(c2, dtype=dtype, inner_tol=1e-7)
+    try:
+        S.factor()
+        be = factor_backward_error(S, c2, 1)
+        print(f"c2 {dtype}: factor backward error {be}")
+        assert be["t"] == 1024 and be["tile_rows"] == 8
+        assert be["rel_fro"] <= BACKWARD_BOUND[dtype]
+    finally:
+        S.close()

@@ -45,7 +45,11 @@ def _net(d_in, H, d_out, batch, seed):
     return net, p
 
 
-SHAPES = [(70, 96, 40, 75), (130, 64, 200, 33), (4098 // 8, 128, 256, 130)]
+# small ragged shapes, then the production network of the time sequence
+# (t = 1024: inputs 2 (2t) + 2, outputs 2t, hidden 512) at the batch of one
+# step (63 interfaces) and a training batch of 512 rows
+SHAPES = [(70, 96, 40, 75), (130, 64, 200, 33), (4098 // 8, 128, 256, 130), (4098, 512, 2048, 63),
+          (4098, 512, 2048, 512)]
 
 
 @pytest.mark.parametrize("d_in,H,d_out,batch", SHAPES)
@@ -268,13 +272,23 @@ def test_guess_seeds_the_reduced_solve(c1_setup):
 
 
 # ------------------------------------------------------------ gain
-def test_learned_guess_gain_on_time_sequence():
+def test_learned_guess_judge_on_time_sequence():
     """Implicit-Euler convection-diffusion (128 x 128, |v| = 50 rotating 1.2
     degrees per step, dt = 1e-3, p = 8): 60 plain steps train the network,
-    the next 20 compare the judged learned guess with the previous-step
-    guess on the reduced residual and on inner iterations."""
+    the next 20 solve each step twice, once from the previous-step guess and
+    once from the judged guess.
+
+    What is asserted: the network learns (loss falls fivefold), its guess
+    starts the reduced solve from a smaller reduced residual than the
+    previous step's solution, the judge takes whichever start has the
+    smaller residual, and every solve converges.  What is not asserted is an
+    iteration gain: there is none.  The reduced BiCGStab gains about a
+    decade per iteration, so a start residual a few times smaller is worth a
+    fraction of an iteration, and the measured totals over the 20 steps are
+    about equal (317 inner iterations from the judged guess, 315 from the
+    previous step's)."""
     from paper_1008_1700_amd import ddps, guess
-    torch = torch_cuda()
+    torch_cuda()
     nx = ny = 128
     p = 8
     A1, _ = configs.c4_matrix(1, nx, ny)
@@ -298,13 +312,11 @@ def test_learned_guess_gain_on_time_sequence():
     il = sum(r["learn_inner"] for r in ev)
     print(f"judge residual prev/learned (median) {np.median(rp):.3e} / {np.median(rl):.3e}; "
           f"learned chosen {sum(r['learned'] for r in ev)}/20; inner iterations prev {ip} learned {il}")
-    # the judge's measure: the learned guess starts the reduced solve from a
-    # residual at least 2x smaller and is chosen at most steps; the reduced
-    # BiCGStab gains about a decade per iteration, so this is worth a fraction
-    # of an iteration here and iterations must merely not get worse
     assert np.median(rl) < 0.5 * np.median(rp)
-    assert sum(r["learned"] for r in ev) >= 15
-    assert il <= 1.05 * ip
+    assert all(r["learned"] == (r["r_learn"] < r["r_prev"]) for r in ev)
+    # both runs of a step do the same work up to the start: iteration counts
+    # stay within a few per step of each other (recorded, not a gain)
+    assert abs(il - ip) <= 3 * len(ev)
 
 
 @pytest.mark.parametrize("retrieval", [0, 1])

@@ -370,3 +370,21 @@ def test_mmatrix_bounds_on_c1_match_the_dense_inverse():
     exact1 = np.abs(Ad).sum(axis=0).max() * np.abs(inv).sum(axis=0).max()
     est1 = O.cond1_dense_estimate(A)
     assert exact1 / 3.0 <= est1 <= exact1 * (1.0 + 1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_direct_solve_matches_dense_solve_and_residual(seed):
+    """The sparse direct solve that stands for the exact solution of a large
+    system: against LAPACK's dense solve on a small nonsymmetric banded
+    system (one and several columns), and by its residual."""
+    d = configs.small_banded(3, [70, 90, 80], 12, 40 + seed)
+    A = d["A"].scipy()
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((A.shape[0], 3))
+    X = O.direct_solve(A, F)
+    ref = np.linalg.solve(A.toarray(), F)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * np.max(np.abs(ref))
+    x1 = O.direct_solve(A, F[:, 0])
+    assert x1.shape == (A.shape[0],) and np.array_equal(x1, X[:, 0])
+    r = F - A @ X
+    assert np.max(np.abs(r)) <= 1e-13 * np.max(np.abs(F))

@@ -280,10 +280,12 @@ def kappa_inf_certificate(S, d):
     ones = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.zeros_like(ones)
     ddps.ddps_factor(S.h)
+    # any y > 0 with A y > 0 certifies; a residual of 1e-10 makes the bracket
+    # tight without driving a badly conditioned system to the FP64 floor
     if S.opt.max_rhs > 1:
-        ddps.ddps_solve_many(S.h, ones.reshape(1, n), y.reshape(1, n), 1e-12, check=False)
+        ddps.ddps_solve_many(S.h, ones.reshape(1, n), y.reshape(1, n), 1e-10, check=False)
     else:
-        S.solve(ones, y, 1e-12, check=False)
+        S.solve(ones, y, 1e-10, check=False)
     yh = y.cpu().numpy()
     if not np.all(yh > 0):
         return None

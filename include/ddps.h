@@ -70,11 +70,15 @@ typedef struct {
   int32_t outer_maxit;     /* maximum outer iterations (Section 4 uses 1000) */
   int32_t outer_method;    /* 0 = preconditioned BiCGStab (Section 4), 1 = iterative refinement
                               x += P^{-1}(f - Ax).  Under refinement a step's inner tolerance is
-                              never below inner_tol; it is raised to 0.1 tol ||f|| / ||r|| (at
-                              most 1e-2), and to 0.1 rho when a step at inner_tol cut the
-                              residual by a ratio rho <= 1e-2 (the factors, not the inner solve,
-                              then limit the steps; stopped once a loosened step cuts it by less
-                              than 10 rho) */
+                              inner_tol, raised to 0.1 tol ||f|| / ||r|| when that is larger (at
+                              most 1e-2).  rho_f is the residual ratio of the last step taken at
+                              that tolerance; once rho_f <= 1e-2 (the factors, not the inner
+                              solve, then limit the steps), later steps are loosened to
+                              0.1 rho_f.  A loosened step whose ratio exceeds loosen_ratio *
+                              rho_f is undone (x and its residual restored) and redone at the
+                              unloosened tolerance, and loosening stops for the solve; so every
+                              kept loosened step cuts the residual by at most loosen_ratio *
+                              rho_f */
   int32_t guess;           /* 0: reduced solve starts at z^ = 0; 1: from the vector given to
                               ddps_set_guess (kept until replaced) */
   int32_t use_x0;          /* 1: x is read as the initial outer iterate */
@@ -107,6 +111,9 @@ typedef struct {
                               then a forward and a backward substitution per application.
                               A zero pivot there is reported as DDPS_E_SINGULAR with
                               bad_block = p and bad_row = the reduced row */
+  double loosen_ratio;     /* refinement: the factor by which a loosened step may fall short
+                              of rho_f before it is undone (see outer_method); 0 = 10,
+                              negative = never loosen */
 } ddps_options;
 
 typedef struct {
@@ -120,6 +127,8 @@ typedef struct {
   double t_setup_ms, t_factor_ms, t_solve_ms;   /* device time of the last call of each */
   int32_t bad_block;        /* DDPS_E_SINGULAR: block of the first bad pivot, else -1 */
   int64_t bad_row;          /* DDPS_E_SINGULAR: global row of that pivot, else -1 */
+  int32_t loosened_steps;   /* refinement steps taken at a loosened inner tolerance */
+  int32_t undone_steps;     /* of these, steps undone and redone (see outer_method) */
 } ddps_info;
 
 /* Fills *opt with the defaults: delta 0, FP64 factors, inner_tol 1e-12,

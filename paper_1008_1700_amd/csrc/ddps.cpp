@@ -167,6 +167,11 @@ struct ddps_ctx {
   hipStream_t fstream = nullptr;          // internal stream of the factorisation
   std::vector<hipStream_t> gstream;       // one per group beyond the first
   std::vector<hipEvent_t> gevent;
+  // fork/join events of a factorisation being captured: created for each
+  // capture and used by nothing else, so that no event object recorded inside
+  // a capture is ever recorded or waited on outside it (and the reverse)
+  hipEvent_t cap_fork = nullptr;
+  std::vector<hipEvent_t> cap_gevent;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -307,6 +312,13 @@ struct ddps_ctx {
     if (graph) hipGraphDestroy(graph);
     graph_exec = nullptr;
     graph = nullptr;
+    drop_capture_events();
+  }
+  void drop_capture_events() {
+    if (cap_fork) hipEventDestroy(cap_fork);
+    for (auto e : cap_gevent) hipEventDestroy(e);
+    cap_fork = nullptr;
+    cap_gevent.clear();
   }
   hipEvent_t get_event() {
     if (!ev_pool.empty()) {
@@ -1138,14 +1150,17 @@ int enqueue_factor(ddps_ctx* h) {
     HIPCHK(hipGetLastError());
     return DDPS_OK;
   }
-  HIPCHK(hipEventRecord(h->fork_ev, f));
-  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->gstream[g - 1], h->fork_ev, 0));
+  hipEvent_t fork = h->capturing ? h->cap_fork : h->fork_ev;
+  const std::vector<hipEvent_t>& gev = h->capturing ? h->cap_gevent : h->gevent;
+  if (!fork || (int)gev.size() < G - 1) return DDPS_E_STATE;
+  HIPCHK(hipEventRecord(fork, f));
+  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->gstream[g - 1], fork, 0));
   if ((rc = run_schedule(h, h->sch_group[0], 1, 0, 0, TK_GEMM, f))) return rc;
   for (int g = 1; g < G; ++g) {
     if ((rc = run_schedule(h, h->sch_group[g], 1, 0, 0, TK_GEMM, h->gstream[g - 1]))) return rc;
-    HIPCHK(hipEventRecord(h->gevent[g - 1], h->gstream[g - 1]));
+    HIPCHK(hipEventRecord(gev[g - 1], h->gstream[g - 1]));
   }
-  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(f, h->gevent[g - 1], 0));
+  for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(f, gev[g - 1], 0));
   if (h->tip_nseg > 0) pack_tips(h->sdt, h->p, h->t, h->d_blk, h->d_spikes, h->d_tips, f);
   if ((rc = run_schedule(h, h->sch_rfac, 1, 0, 0, TK_GEMM, f, TK_RFAC))) return rc;
   HIPCHK(hipGetLastError());
@@ -1536,6 +1551,7 @@ void ddps_default_options(ddps_options* o) {
   o->norm = 0;
   o->work_slots = 0;
   o->reduced_solve = 0;
+  o->loosen_ratio = 0.0;
 }
 
 const char* ddps_status_string(int s) {
@@ -1602,7 +1618,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
       o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
       o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0 ||
-      o.reduced_solve < 0 || o.reduced_solve > 1) {
+      o.reduced_solve < 0 || o.reduced_solve > 1 || std::isnan(o.loosen_ratio)) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1857,6 +1873,13 @@ int ddps_factor(ddps_handle h) {
   HIPCHK(hipStreamWaitEvent(h->fstream, h->fork_ev, 0));
   if (h->use_graph) {
     if (!h->graph_exec) {
+      h->drop_capture_events();
+      HIPCHK(hipEventCreateWithFlags(&h->cap_fork, hipEventDisableTiming));
+      for (size_t g = 0; g < h->gstream.size(); ++g) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->cap_gevent.push_back(e);
+      }
       h->capturing = true;
       hipError_t e = hipStreamBeginCapture(h->fstream, hipStreamCaptureModeThreadLocal);
       int rc = e == hipSuccess ? enqueue_factor(h) : DDPS_E_HIP;
@@ -1943,6 +1966,7 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   double outer = 0;
   int64_t inner_total = 0;
   int apps = 0;
+  int undone = 0, loosened_n = 0;   // refinement steps undone / taken loosened
   bool breakdown = false;
   std::vector<int> its;
   int bk = 0;
@@ -1967,15 +1991,21 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   };
   if (h->opt.outer_method == 1) {
     // iterative refinement: x += P^{-1} (f - A x).
-    // rho_f is the residual ratio of the last step whose inner solve was not
-    // loosened by rho_f itself.  When it is at most 1e-2 but far above
-    // inner_tol, the factors (not the inner solve) limit a step, and later
-    // steps ask the inner solve for 0.1 rho_f only.  Such a step never
-    // updates rho_f, and if it cuts the residual by less than 10 rho_f the
-    // loosening stops for the rest of the solve; so every loosened step still
-    // cuts the residual at least tenfold.
+    // A step's inner tolerance is inner_tol, or the end-game value
+    // 0.1 tol ||f|| / ||r|| when larger (at most 1e-2).  rho_f is the
+    // residual ratio of the last step taken at that tolerance.  When rho_f is
+    // at most 1e-2 but far above the tolerance, the factors (not the inner
+    // solve) limit a step, and later steps ask the inner solve for 0.1 rho_f
+    // only.  Such a loosened step never updates rho_f.  If its ratio exceeds
+    // guard * rho_f, x and its residual are restored from before the step,
+    // loosening stops for the rest of the solve, and the step is redone at
+    // the unloosened tolerance; so every loosened step that is kept cuts the
+    // residual by at most guard * rho_f (the undone one still counts as an
+    // outer iteration and an application).
     double rho_f = -1.0;
-    bool loosen_off = false;
+    bool loosen_off = h->opt.loosen_ratio < 0.0;
+    undone = loosened_n = 0;
+    const double guard = h->opt.loosen_ratio > 0.0 ? h->opt.loosen_ratio : 10.0;
     std::vector<double> rprev;
     while (!all_conv(cur()) && outer < h->opt.outer_maxit) {
       double worst = 0.0;   // largest ||r||/||f|| still above the tolerance
@@ -1986,6 +2016,8 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       if (loosened) itol = 0.1 * rho_f;
       if (worst > 0) itol = std::min(1e-2, std::max(itol, 0.1 * tol / worst));
       rprev = cur();
+      // a loosened step may be undone: keep x (d_rto is free under refinement)
+      if (loosened) HIPCHK(hipMemcpyAsync(h->d_rto, h->d_xo, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
       if ((rc = papply(h->d_ro, h->d_z))) return rc;
       // columns already converged keep their x
       Coef3 cf{};
@@ -1998,9 +2030,16 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
       double rho = 0.0;
       for (int j = 0; j < k; ++j)
         if (rprev[j] > 0 && !conv_col(j, rprev[j])) rho = std::max(rho, cur()[j] / rprev[j]);
-      if (!loosened) rho_f = rho;
-      else if (rho > 10.0 * rho_f) loosen_off = true;
       outer += 1;
+      if (!loosened) {
+        rho_f = rho;
+      } else if (rho > guard * rho_f) {
+        loosen_off = true;
+        HIPCHK(hipMemcpyAsync(h->d_xo, h->d_rto, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
+        if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
+        ++undone;
+      }
+      if (loosened) ++loosened_n;
     }
   } else {
     // preconditioned BiCGStab (Templates form), convergence tested after
@@ -2117,6 +2156,8 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
     info->t_solve_ms = h->t_solve_ms;
     info->bad_block = h->bad_block;
     info->bad_row = h->bad_row;
+    info->loosened_steps = loosened_n;
+    info->undone_steps = undone;
   }
   if (ok) return DDPS_OK;
   if (breakdown) return DDPS_E_BREAKDOWN;

@@ -49,6 +49,7 @@ class ddps_options(ctypes.Structure):
         ("norm", ctypes.c_int32),
         ("work_slots", ctypes.c_int32),
         ("reduced_solve", ctypes.c_int32),
+        ("loosen_ratio", ctypes.c_double),
     ]
 
 
@@ -65,6 +66,8 @@ class ddps_info(ctypes.Structure):
         ("t_solve_ms", ctypes.c_double),
         ("bad_block", ctypes.c_int32),
         ("bad_row", ctypes.c_int64),
+        ("loosened_steps", ctypes.c_int32),
+        ("undone_steps", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -413,7 +416,7 @@ class Solver:
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
                  mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0,
-                 reduced="bicgstab"):
+                 reduced="bicgstab", loosen_ratio=0.0):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -434,6 +437,7 @@ class Solver:
         o.norm = int(norm)
         o.work_slots = int(work_slots)
         o.reduced_solve = 1 if reduced == "direct" else 0
+        o.loosen_ratio = float(loosen_ratio)
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

@@ -415,3 +415,33 @@ def test_c1_refactor_values_and_guess(c1):
         assert info.inner_iters_avg <= 3
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("ratio", [-1.0, 0.0, 1e-300])
+def test_loosened_refinement_steps(c1, ratio):
+    """Refinement with bf16x3 factors on C1: each step cuts the residual by a
+    ratio the factors set, so later steps may loosen their inner solve.
+    ratio < 0 never loosens; 0 keeps the default guard (10 rho_f); a guard
+    of 1e-300 undoes the first loosened step (x and residual restored), stops
+    loosening and redoes the step.  Every form must converge to the same bar
+    against the oracle's direct solve."""
+    from oracle import ddps_oracle as O
+    A = c1["A"]
+    S = make_solver(c1, dtype="bf16x3", inner_tol=1e-12, outer="refine", loosen_ratio=ratio)
+    try:
+        S.factor()
+        x = dev_vec(np.zeros(A.n))
+        rc, info = S.solve(dev_vec(c1["f"]), x, 1e-12)
+        ref = O.direct_solve(A.scipy(), c1["f"])
+        print(f"loosen_ratio {ratio}: {info.as_dict()}")
+        assert rc == 0 and info.relres_inf <= 1e-12
+        assert relerr(host(x), ref) <= 1e-8
+        if ratio < 0:
+            assert info.loosened_steps == 0 and info.undone_steps == 0
+        elif ratio == 1e-300:
+            # the first loosened step is undone, and no later step loosens
+            assert info.loosened_steps == 1 and info.undone_steps == 1
+        else:
+            assert info.loosened_steps >= 1 and info.undone_steps <= 1
+    finally:
+        S.close()

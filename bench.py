@@ -183,7 +183,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
         mode=mode, retrieval=retrieval, reduced=reduced, rc=rc, ms_per_step=ms, rhs=k,
         factor_ms=info.t_factor_ms, solve_ms=info.t_solve_ms,
         outer_iters=info.outer_iters, inner_iters_avg=info.inner_iters_avg,
-        applications=info.applications,
+        applications=info.applications, loosened_steps=info.loosened_steps, undone_steps=info.undone_steps,
         relres_inf=float(np.max(np.max(np.abs(r), axis=0) / nf)),
         relerr_xstar=float(np.max(np.linalg.norm(X - xst, axis=0) / np.linalg.norm(xst, axis=0))),
         kernel=dict(kind=timing_kind, launches_per_step=tim["launches"], ms_per_step=tim["ms"],

@@ -127,6 +127,7 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
     if G is not None:
         c1 = ddps.ddps_guess_counts(S.h)
         gstats["chosen_in_timed_steps"] = {q: c1[q] - c0[q] for q in c1}
+        gstats["trial"] = ddps.ddps_guess_trial(S.h)
         G.attach(False)
         if compare_steps > 0:
             step()

@@ -114,6 +114,12 @@ typedef struct {
   double loosen_ratio;     /* refinement: the factor by which a loosened step may fall short
                               of rho_f before it is undone (see outer_method); 0 = 10,
                               negative = never loosen */
+  int32_t gemv_sums;       /* FP32 factor storage, 4 or more right-hand sides: the tile and
+                              spike products of the solve phase (block sweeps of step 6.1, the
+                              reduced-matrix products, the retrieval) run as 0 = FP32 products
+                              with FP32 sums on the matrix cores (default), 1 = FP64 sums on
+                              the vector units.  Either way the sums of four column ranges are
+                              added in FP64, and vectors, dots and residuals stay FP64 */
 } ddps_options;
 
 typedef struct {
@@ -430,7 +436,11 @@ int ddps_residual_norms_noalloc(int64_t n, int32_t k, const int64_t* row_ptr, co
  * After 8 reduced solves in a row in which the network's candidate was not
  * the smallest, the network is retired: the reduced solves start from zero
  * (the method's start) without trying candidates, until a network is
- * attached again.
+ * attached again.  A smaller starting residual does not always mean fewer
+ * iterations, so the first reduced solves after attaching also run a trial:
+ * every other one leaves the network out of the choice.  Once each arm has
+ * 8 solves, the network is retired unless its solves took at least half an
+ * inner iteration fewer on average (ddps_guess_trial reports the arms).
  * The network is used, not owned: keep it alive while attached.  Buffers for
  * the network's inputs and outputs are allocated here (not during solves).
  * Errors: DDPS_E_ARG (shape or stream mismatch), DDPS_E_NOMEM. */
@@ -440,6 +450,13 @@ int ddps_set_guess_model(ddps_handle h, ddps_mlp net);
  * from the network after trying the candidates, and those started without
  * trying them (network retired), over the handle's lifetime. */
 int ddps_guess_counts(ddps_handle h, int64_t* counts);
+
+/* The trial of the attached network against its absence (see
+ * ddps_set_guess_model): host int64[2] solves and double[2] mean inner
+ * iterations per solve, index 0 without the network, 1 with it; *state:
+ * 0 = running, 1 = done and the network kept, 2 = the network retired (by
+ * the trial or by 8 lost reduced solves in a row).  Errors: DDPS_E_ARG. */
+int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t* state);
 
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);

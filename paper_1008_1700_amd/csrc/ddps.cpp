@@ -145,6 +145,7 @@ struct ddps_ctx {
          *d_v = nullptr, *d_s = nullptr, *d_tv = nullptr, *d_guess = nullptr;
   double *d_mp = nullptr, *d_ms = nullptr;  // M^{-1}p, M^{-1}s of the locally preconditioned inner solve
   double *d_part_buf = nullptr, *d_sums = nullptr, *d_out = nullptr;
+  double* d_red1 = nullptr;   // first-level sums of two-level reductions (kReduceGroups x kMaxRhs x 2)
   KState* d_state = nullptr;
   int32_t* d_flag = nullptr;
   double *d_fo = nullptr, *d_xo = nullptr, *d_ro = nullptr, *d_z = nullptr, *d_rto = nullptr,
@@ -188,6 +189,14 @@ struct ddps_ctx {
   float *d_gX = nullptr, *d_gS = nullptr, *d_gY = nullptr;
   int64_t guess_counts[3] = {0, 0, 0};   // reduced solves started from 0, from g^, from the network
   int gnet_losses = 0;                    // reduced solves in a row in which the network's candidate lost
+  // trial of the network against its absence: reduced solves alternate
+  // between starting from the best of {0, g^, network} (arm 1) and of
+  // {0, g^} (arm 0); arm of each column of the current application, the
+  // solves and inner iterations per arm, and the alternation counter
+  std::vector<int> garm;
+  int64_t gtrial_n[2] = {0, 0}, gtrial_its[2] = {0, 0};
+  int64_t gtrial_seq = 0;
+  bool gtrial_done = false;
   int64_t gnet_skipped = 0;               // reduced solves started without trying (the network was retired)
   // last solve
   int last_k = 0;
@@ -441,10 +450,16 @@ struct ScheduleBuilder {
       std::stable_sort(o + lo, o + lo + cnt, [&](int32_t a, int32_t b) { return klen[a] > klen[b]; });
     }
   }
+  // GEMV kernel form of the current launch (see launch_gemv); the matrix
+  // cores take FP32 operands only when the handle's factors are not FP64
+  int gemv_form() const {
+    if (!gemv_aligned) return 0;
+    return (h->opt.factor_dtype != DDPS_F64 && h->opt.gemv_sums == 0) ? 2 : 1;
+  }
   void end(std::vector<Launch>& out) {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : kind == LK_PANEL ? (int64_t)panel.size()
                                                                               : (int64_t)gemv.size()) - off;
-    const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
+    const int mode = kind == LK_GEMM ? finish_gemm() : gemv_form();
     if (cnt > 0 && nwg > 0) {
       out.push_back({kind, off, (int)cnt, nwg, flops, bytes, mode, kind == LK_GEMM ? cur_ord : -1});
       if (kind == LK_GEMM) ++h->mode_cursor;
@@ -452,7 +467,7 @@ struct ScheduleBuilder {
   }
   Launch end_one() {
     const int64_t cnt = (kind == LK_GEMM ? (int64_t)gemm.size() : (int64_t)gemv.size()) - off;
-    const int mode = kind == LK_GEMM ? finish_gemm() : (gemv_aligned ? 1 : 0);
+    const int mode = kind == LK_GEMM ? finish_gemm() : gemv_form();
     return Launch{kind, off, (int)cnt, nwg, flops, bytes, mode, kind == LK_GEMM ? cur_ord : -1};
   }
   void add_gemm(const void* A, int lda, const void* B, int ldb, const void* C0, int ldc0, void* D, int ldd,
@@ -1066,7 +1081,7 @@ int run_launch(ddps_ctx* h, const Launch& L, int R, int64_t ldx, int64_t ldy, co
       launch_tipmv(h->sdt, R, h->tip_nseg, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
       break;
     default:
-      launch_gemv(h->sdt, R, L.mode == 1, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
+      launch_gemv(h->sdt, R, L.mode, h->d_gemv + L.off, L.nprob, L.nwg, ldx, ldy, dotv, partial, stop, s);
       break;
   }
   h->tim_end(tkind, a, L.flops * (L.kind == LK_GEMV || L.kind == LK_TIPMV ? R : 1), L.bytes, s);
@@ -1311,15 +1326,15 @@ int inner_solve(ddps_ctx* h, int k, int use_guess, double tol, int maxit, std::v
       // right preconditioning: v = G^ M^{-1} p, t = G^ M^{-1} s, x += a M^{-1} p + w M^{-1} s
       if (prec) run_launch(h, h->l_lp, R, m, m, nullptr, nullptr, stop, TK_RSPMV);
       run_launch(h, prec ? h->l_pvh : h->l_pv, R, m, m, h->d_rt, h->d_part_buf, stop, TK_RSPMV);
-      reduce2(R, h->W1, h->d_part_buf, S1, stop, s);
+      reduce2(R, h->W1, h->d_part_buf, S1, stop, s, h->d_red1);
       bicg_s(R, it, m, S1, h->d_state, h->d_r, h->d_v, h->d_s, h->d_part_buf, W2, s);
-      reduce2(R, W2, h->d_part_buf, S2, stop, s);
+      reduce2(R, W2, h->d_part_buf, S2, stop, s, h->d_red1);
       if (prec) run_launch(h, h->l_ls, R, m, m, nullptr, nullptr, stop, TK_RSPMV);
       run_launch(h, prec ? h->l_sth : h->l_st, R, m, m, h->d_s, h->d_part_buf, stop, TK_RSPMV);
-      reduce2(R, h->W1, h->d_part_buf, S3, stop, s);
+      reduce2(R, h->W1, h->d_part_buf, S3, stop, s, h->d_red1);
       bicg_xr(R, it, m, tol, S1, S2, S3, h->d_state, h->d_zh, h->d_p, h->d_s, h->d_tv, h->d_r, h->d_rt,
               h->d_part_buf, W2, s, prec ? h->d_mp : nullptr, prec ? h->d_ms : nullptr);
-      reduce2(R, W2, h->d_part_buf, S4, stop, s);
+      reduce2(R, W2, h->d_part_buf, S4, stop, s, h->d_red1);
       bicg_p(R, it, maxit, m, tol, S1, S2, S3, S4, h->d_state, h->d_r, h->d_p, h->d_v, W2, s);
     }
     HIPCHK(hipGetLastError());
@@ -1391,8 +1406,14 @@ int learned_start(ddps_ctx* h, int k) {
   std::vector<double> nb, nl, ng, unused;
   if ((rc = dots(h, m, h->d_r, h->d_r, h->d_rt, h->d_rt, nb, nl))) return rc;
   if ((rc = dots(h, m, h->d_gh, h->d_gh, nullptr, nullptr, ng, unused))) return rc;
+  h->garm.assign(k, -1);
   for (int j = 0; j < k; ++j) {
     double* col = h->d_guess + (int64_t)j * m;
+    if (!h->gtrial_done) {
+      // trial: every other reduced solve leaves the network out
+      h->garm[j] = (int)(h->gtrial_seq++ & 1);
+      if (h->garm[j] == 0) nl[j] = std::numeric_limits<double>::infinity();
+    }
     if (ng[j] <= nb[j] && ng[j] <= nl[j]) {
       fill_f64(col, m, 0.0, s);
       ++h->guess_counts[0];
@@ -1402,12 +1423,17 @@ int learned_start(ddps_ctx* h, int k) {
     } else {
       ++h->guess_counts[2];
     }
-    h->gnet_losses = (nl[j] < ng[j] && nl[j] < nb[j]) ? 0 : h->gnet_losses + 1;
+    if (h->gtrial_done || h->garm[j] == 1)
+      h->gnet_losses = (nl[j] < ng[j] && nl[j] < nb[j]) ? 0 : h->gnet_losses + 1;
   }
   if (k < R) fill_f64(h->d_guess + (int64_t)k * m, m * (R - k), 0.0, s);
   HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
+
+// A network is retired (no candidates tried) once its candidate has lost
+// kRetire reduced solves in a row, or lost the trial against its absence.
+constexpr int kRetire = 8;
 
 // z = P^{-1} y (k columns, device, leading dims ldy/ldz).  Reduced vectors
 // are left in d_gh / d_zh.
@@ -1425,7 +1451,6 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
     // the network is retired (no candidates tried; the zero start of the
     // method) once it has lost kRetire reduced solves in a row, until a
     // network is attached again
-    constexpr int kRetire = 8;
     if (h->gnet_losses < kRetire) {
       if ((rc = learned_start(h, k))) return rc;
       use_guess = 1;
@@ -1433,9 +1458,30 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
       h->gnet_skipped += k;
     }
   }
+  const bool trial = h->gnet && !h->gtrial_done && (int)h->garm.size() == k && use_guess;
   std::vector<int> st;
   rc = inner_solve(h, k, use_guess, inner_tol, h->opt.inner_maxit, iters, st);
   if (rc) return rc;
+  if (trial) {
+    // the network stays only if its solves take at least half an iteration
+    // fewer on average than the solves without it (its candidate costs two
+    // reduced products per application); otherwise it is retired
+    constexpr int kTrial = 8;
+    for (int j = 0; j < k; ++j) {
+      const int a = h->garm[j];
+      if (a < 0) continue;
+      h->gtrial_n[a] += 1;
+      h->gtrial_its[a] += iters[j];
+    }
+    h->garm.clear();
+    if (h->gtrial_n[0] >= kTrial && h->gtrial_n[1] >= kTrial) {
+      h->gtrial_done = true;
+      // mean counts in half iterations (the inner solve's unit)
+      const double m0 = (double)h->gtrial_its[0] / (double)h->gtrial_n[0];
+      const double m1 = (double)h->gtrial_its[1] / (double)h->gtrial_n[1];
+      if (!(m1 <= m0 - 1.0)) h->gnet_losses = kRetire;
+    }
+  }
   if (breakdown) {
     *breakdown = 0;
     for (int j = 0; j < k; ++j)
@@ -1552,6 +1598,7 @@ void ddps_default_options(ddps_options* o) {
   o->work_slots = 0;
   o->reduced_solve = 0;
   o->loosen_ratio = 0.0;
+  o->gemv_sums = 0;
 }
 
 const char* ddps_status_string(int s) {
@@ -1618,7 +1665,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (!(o.drop_delta >= 0.0 && o.drop_delta <= 1.0) || fac_dtype_code(o.factor_dtype) < 0 || o.inner_maxit < 1 ||
       o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
       o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0 ||
-      o.reduced_solve < 0 || o.reduced_solve > 1 || std::isnan(o.loosen_ratio)) {
+      o.reduced_solve < 0 || o.reduced_solve > 1 || std::isnan(o.loosen_ratio) || o.gemv_sums < 0 ||
+      o.gemv_sums > 1) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1816,6 +1864,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     return fail(rc);
   h->part_cap = Wmax * R * 4;
   if ((rc = h->alloc(h->d_part_buf, h->part_cap)) || (rc = h->alloc(h->d_sums, 5 * 2 * kMaxRhs)) ||
+      (rc = h->alloc(h->d_red1, (int64_t)kReduceGroups * kMaxRhs * 2)) ||
       (rc = h->alloc(h->d_out, 4 * kMaxRhs)) || (rc = h->alloc(h->d_state, 1)) || (rc = h->alloc(h->d_flag, kMaxRhs)))
     return fail(rc);
   // zero every vector buffer once (unused RHS columns stay finite)
@@ -2215,6 +2264,10 @@ int ddps_set_guess_model(ddps_handle h, ddps_mlp net) {
   }
   h->gnet = net;
   h->gnet_losses = 0;
+  h->gtrial_n[0] = h->gtrial_n[1] = h->gtrial_its[0] = h->gtrial_its[1] = 0;
+  h->gtrial_seq = 0;
+  h->gtrial_done = false;
+  h->garm.clear();
   return DDPS_OK;
 }
 
@@ -2222,6 +2275,17 @@ int ddps_guess_counts(ddps_handle h, int64_t* counts) {
   if (!h || !counts) return DDPS_E_ARG;
   for (int q = 0; q < 3; ++q) counts[q] = h->guess_counts[q];
   counts[3] = h->gnet_skipped;
+  return DDPS_OK;
+}
+
+int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t* state) {
+  if (!h || !solves || !mean_iters || !state) return DDPS_E_ARG;
+  for (int a = 0; a < 2; ++a) {
+    solves[a] = h->gtrial_n[a];
+    // the inner solve counts half iterations
+    mean_iters[a] = h->gtrial_n[a] ? 0.5 * (double)h->gtrial_its[a] / (double)h->gtrial_n[a] : 0.0;
+  }
+  *state = h->gnet_losses >= kRetire ? 2 : (h->gtrial_done ? 1 : 0);
   return DDPS_OK;
 }
 

@@ -147,8 +147,11 @@ void launch_gemm(int dtype, int mode, const GemmProb* probs, int nprob, int nwg,
 void gemm_tile_shape(int dtype, int mode, int* bm, int* bn);
 void launch_panel(int dtype, const PanelProb* probs, int nprob, const double* thresh,
                   unsigned long long* bad, hipStream_t s);
-// wide: every problem's A and column stride are 16-byte aligned (k_gemv_w)
-void launch_gemv(int dtype, int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+// form 0: plain (k_gemv); 1: every problem's A and column stride are 16-byte
+// aligned (k_gemv_w); 2: aligned, and for FP32 operands with 4 or more
+// right-hand sides run on the FP32 matrix cores with FP32 sums (k_gemv_mf32),
+// otherwise as form 1
+void launch_gemv(int dtype, int nrhs, int form, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s);
 // reduced-matrix product on the packed tips (same records as launch_gemv,
 // A = first packed row, lda = 2t; nrhs 1 or 2; nseg from tipmv_segments, 0 if
@@ -192,7 +195,12 @@ void vec_gather_reduced(int64_t m, int R, const int64_t* rrow, const double* mas
                         int64_t Np, double* gh, hipStream_t s);
 int vec_grid(int64_t n);
 void vec_apply_mask(int64_t m, int R, const double* mask, double* x, hipStream_t s);
-void reduce2(int R, int W, const double* part, double* out, const int32_t* stop, hipStream_t s);
+// sums of [W][R][2] partials into out[R][2] in a fixed order; with scratch
+// (kReduceGroups x R x 2 doubles) and W > kReduceSplit in two levels
+constexpr int kReduceSplit = 4096;
+constexpr int kReduceGroups = 64;
+void reduce2(int R, int W, const double* part, double* out, const int32_t* stop, hipStream_t s,
+             double* scratch = nullptr);
 void bicg_init(int R, int64_t m, int use_guess, const double* gh, double* x, const double* v, double* r,
                double* rt, double* p, double* part, int W, hipStream_t s);
 void bicg_init_state(int R, int k, double tol, const double* sums, KState* st, hipStream_t s);

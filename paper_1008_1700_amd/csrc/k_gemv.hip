@@ -456,6 +456,142 @@ void pack_tips(int dtype, int p, int t, const BlockInfo* blocks, const void* spi
   else hipLaunchKernelGGL(k_pack_tips<float>, g, b, 0, s, blocks, t, (const float*)spikes, (float*)tips);
 }
 
+// ------------------------------------------------------------------------
+// Many right-hand sides (R >= 4) on FP32 operands, as products on the FP32
+// matrix cores (16x16x4).  One
+// workgroup per 64-row slab; its 4 waves take interleaved groups of 4
+// columns.  Lane l loads rows 4(l & 15) .. +3 of column c + (l >> 4) (one
+// float4; a wave load covers 64 rows x 4 columns), and the four products q
+// take its component q, so product q accumulates the slab rows 4i + q.  The
+// second operand of lane l is x(c + (l >> 4), rhs l & 15) rounded to FP32
+// (0 for rhs >= R).  The sums are FP32, each over a quarter of the columns;
+// the four quarters are added in FP64 in a fixed order.  Register v of
+// accumulator q in lane l holds slab row 16 (l >> 4) + 4 v + q, rhs l & 15.
+// Triangular problems clip the column range as the other kernels do; the
+// masks of packed triangles change only the columns [r0, r0 + 64) of a
+// slab, so only loads of those columns go through the selects.
+// ------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void k_gemv_mf32(const GemvProb* __restrict__ probs, int nprob,
+                                                   int64_t ldx, int64_t ldy,
+                                                   const double* __restrict__ dotv,
+                                                   double* __restrict__ partial,
+                                                   const int32_t* __restrict__ stop) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  static_assert(R >= 1 && R <= 16, "right-hand sides per product");
+  constexpr int U = 4;   // column groups in flight per wave
+  __shared__ float red[4][64][R];
+  if (stop) {
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < R; ++j) all &= stop[j] != KS_RUNNING;
+    if (all) return;
+  }
+  const int wg = blockIdx.x;
+  const GemvProb P = probs[find_gemv(probs, nprob, wg)];
+  const int r0 = (wg - P.wg0) * 64;
+  int cb = P.cb, ce = P.ce;
+  if (P.tri == 1) ce = min(ce, r0 + 64);
+  if (P.tri == 2) cb = max(cb, r0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int fl = P.flags;
+  const bool mlu = fl & V_A_MLU, mup = fl & V_A_MUP, mlo = fl & V_A_MLO;
+  const bool masked = mlu || mup || mlo;
+  const float* __restrict__ A = (const float*)P.A + r0 + 4 * li;
+  const int64_t lda = P.lda;
+  const int split = P.split;
+  const bool live = li < R;
+  const int jx = live ? li : 0;
+  f32x4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto xval = [&](int cc) __attribute__((always_inline)) -> float {
+    const double v = cc < split ? P.x1[cc + jx * ldx] : P.x2[(cc - split) + jx * ldx];
+    return live ? (float)v : 0.f;
+  };
+  // the packed-triangle masks on the 4 rows of a lane's load of column cc
+  auto fix = [&](float4& a, int cc) __attribute__((always_inline)) {
+    if (masked && cc >= r0 && cc < r0 + 64) {
+      float e[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = r0 + 4 * li + q;
+        if (mlu) e[q] = rr > cc ? e[q] : (rr == cc ? 1.f : 0.f);
+        if (mup) e[q] = rr <= cc ? e[q] : 0.f;
+        if (mlo) e[q] = rr >= cc ? e[q] : 0.f;
+      }
+      a = float4{e[0], e[1], e[2], e[3]};
+    }
+  };
+  auto mma = [&](const float4& a, float x) __attribute__((always_inline)) {
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x, acc[3], 0, 0, 0);
+  };
+  // wave g takes the column groups cb + 4 (g + 4 s), s = 0, 1, ...
+  int c = cb + 4 * g;
+  for (; c + 16 * (U - 1) + 3 < ce; c += 16 * U) {
+    float4 a[U];
+    float x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int cc = c + 16 * u + lk;
+      a[u] = *(const float4*)(A + (int64_t)cc * lda);
+      x[u] = xval(cc);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      fix(a[u], c + 16 * u + lk);
+      mma(a[u], x[u]);
+    }
+  }
+  for (; c < ce; c += 16) {
+    const int cc = c + lk;
+    const bool in = cc < ce;
+    float4 a = in ? *(const float4*)(A + (int64_t)cc * lda) : float4{0.f, 0.f, 0.f, 0.f};
+    fix(a, cc);
+    mma(a, in ? xval(cc) : 0.f);
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[g][16 * lk + 4 * v + q][li] = acc[q][v];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int r = r0 + lane;
+    double dot[R], dd[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      double s = (double)red[0][lane][j] + (double)red[1][lane][j] + (double)red[2][lane][j] + (double)red[3][lane][j];
+      if (fl & V_MASK) s *= P.mask[r];
+      if (fl & V_NEG) s = -s;
+      if (fl & V_YIN) s += P.yin[r + j * ldy];
+      if (r >= P.row_skip) P.yout[r + j * ldy] = s;
+      dot[j] = (fl & V_DOT) ? dotv[P.dot_off + r + j * ldy] * s : 0.0;
+      dd[j] = (fl & V_DOT2) ? s * s : 0.0;
+    }
+    if (fl & V_DOT) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        double v = dot[j], w = dd[j];
+        for (int off = 32; off > 0; off >>= 1) {
+          v += __shfl_xor(v, off, 64);
+          w += __shfl_xor(w, off, 64);
+        }
+        if (lane == 0) {
+          partial[((int64_t)wg * R + j) * 2 + 0] = v;
+          partial[((int64_t)wg * R + j) * 2 + 1] = w;
+        }
+      }
+    }
+  }
+}
+
 template <typename T>
 static void gemv_dispatch(int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                           int64_t ldy, const double* dotv, double* partial, const int32_t* stop,
@@ -472,11 +608,18 @@ static void gemv_dispatch(int nrhs, bool wide, const GemvProb* probs, int nprob,
 #undef DDPS_GEMV
 }
 
-void launch_gemv(int dtype, int nrhs, bool wide, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
+void launch_gemv(int dtype, int nrhs, int form, const GemvProb* probs, int nprob, int nwg, int64_t ldx,
                  int64_t ldy, const double* dotv, double* partial, const int32_t* stop, hipStream_t s) {
   if (nwg <= 0 || nprob <= 0) return;
-  if (dtype == 0) gemv_dispatch<double>(nrhs, wide, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
-  else gemv_dispatch<float>(nrhs, wide, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
+  if (dtype == 1 && form == 2 && nrhs >= 4) {
+    if (nrhs == 4)
+      hipLaunchKernelGGL((k_gemv_mf32<4>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop);
+    else
+      hipLaunchKernelGGL((k_gemv_mf32<8>), dim3(nwg), dim3(256), 0, s, probs, nprob, ldx, ldy, dotv, partial, stop);
+    return;
+  }
+  if (dtype == 0) gemv_dispatch<double>(nrhs, form >= 1, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
+  else gemv_dispatch<float>(nrhs, form >= 1, probs, nprob, nwg, ldx, ldy, dotv, partial, stop, s);
 }
 
 }  // namespace ddps

@@ -64,6 +64,37 @@ __global__ __launch_bounds__(256) void k_reduce2(int W, const double* __restrict
     for (int j = 0; j < R; ++j) { out[2 * j] = acc[j][0]; out[2 * j + 1] = acc[j][1]; }
 }
 
+// First level of a two-level reduction of [w][R][2] partials: workgroup b
+// sums the contiguous range w in [b per, (b + 1) per) in fixed order (as
+// k_reduce2 does over all of them) into out1[b][R][2].
+template <int R>
+__global__ __launch_bounds__(256) void k_reduce2_part(int W, int per, const double* __restrict__ part,
+                                                      double* __restrict__ out1, const int32_t* __restrict__ stop) {
+  __shared__ double sh[4][R][2];
+  if (stop) {
+    bool all = true;
+    for (int j = 0; j < R; ++j) all &= stop[j] != KS_RUNNING;
+    if (all) return;
+  }
+  const int w0 = blockIdx.x * per, w1 = min(W, w0 + per);
+  double acc[R][2];
+#pragma unroll
+  for (int j = 0; j < R; ++j) acc[j][0] = acc[j][1] = 0.0;
+  for (int w = w0 + (int)threadIdx.x; w < w1; w += 256)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      acc[j][0] += part[((int64_t)w * R + j) * 2 + 0];
+      acc[j][1] += part[((int64_t)w * R + j) * 2 + 1];
+    }
+  block_sum<R>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      out1[((int64_t)blockIdx.x * R + j) * 2 + 0] = acc[j][0];
+      out1[((int64_t)blockIdx.x * R + j) * 2 + 1] = acc[j][1];
+    }
+}
+
 __device__ __forceinline__ double sum_of(const double* __restrict__ sums, int j, int q) {
   return sums[2 * j + q];
 }
@@ -602,7 +633,16 @@ void vec_apply_mask(int64_t m, int R, const double* mask, double* x, hipStream_t
   hipLaunchKernelGGL(k_apply_mask, dim3(grid_for(m)), dim3(256), 0, s, m, R, mask, x);
 }
 
-void reduce2(int R, int W, const double* part, double* out, const int32_t* stop, hipStream_t s) {
+void reduce2(int R, int W, const double* part, double* out, const int32_t* stop, hipStream_t s, double* scratch) {
+  if (scratch && W > kReduceSplit) {
+    // one workgroup cannot stream many thousand partials quickly: first
+    // kReduceGroups workgroups over contiguous ranges, then one over theirs
+    const int per = (W + kReduceGroups - 1) / kReduceGroups;
+    const int G = (W + per - 1) / per;
+    DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_reduce2_part<RR>, dim3(G), dim3(256), 0, s, W, per, part, scratch, stop));
+    DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_reduce2<RR>, dim3(1), dim3(256), 0, s, G, scratch, out, stop));
+    return;
+  }
   DDPS_R_DISPATCH(R, hipLaunchKernelGGL(k_reduce2<RR>, dim3(1), dim3(256), 0, s, W, part, out, stop));
 }
 void bicg_init(int R, int64_t m, int use_guess, const double* gh, double* x, const double* v, double* r,

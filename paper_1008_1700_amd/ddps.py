@@ -50,6 +50,7 @@ class ddps_options(ctypes.Structure):
         ("work_slots", ctypes.c_int32),
         ("reduced_solve", ctypes.c_int32),
         ("loosen_ratio", ctypes.c_double),
+        ("gemv_sums", ctypes.c_int32),
     ]
 
 
@@ -122,6 +123,7 @@ _SIGS = {
     "ddps_memory": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "ddps_set_guess_model": (_I32, [_P, _P]),
     "ddps_guess_counts": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "ddps_guess_trial": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
     "ddps_residual_norms": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D), _P]),
     "ddps_residual_norms_noalloc": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D),
                                            _P]),
@@ -394,6 +396,15 @@ def ddps_guess_counts(h):
     return dict(zero=c[0], ghat=c[1], learned=c[2], retired=c[3])
 
 
+def ddps_guess_trial(h):
+    n = (_I64 * 2)()
+    mean = (ctypes.c_double * 2)()
+    st = _I32()
+    _chk(lib().ddps_guess_trial(h, n, mean, ctypes.byref(st)), "ddps_guess_trial")
+    return dict(solves_without=n[0], solves_with=n[1], mean_iters_without=mean[0], mean_iters_with=mean[1],
+                state={0: "running", 1: "kept", 2: "retired"}[st.value])
+
+
 def ddps_memory(h):
     b = ctypes.c_size_t()
     _chk(lib().ddps_memory(h, ctypes.byref(b)), "ddps_memory")
@@ -416,7 +427,7 @@ class Solver:
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
                  mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0,
-                 reduced="bicgstab", loosen_ratio=0.0):
+                 reduced="bicgstab", loosen_ratio=0.0, gemv_sums=0):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -438,6 +449,7 @@ class Solver:
         o.work_slots = int(work_slots)
         o.reduced_solve = 1 if reduced == "direct" else 0
         o.loosen_ratio = float(loosen_ratio)
+        o.gemv_sums = int(gemv_sums)
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

@@ -353,3 +353,46 @@ def test_learned_guess_in_every_application(retrieval):
         G.close()
     finally:
         S.close()
+
+
+def test_untrained_network_is_retired_by_the_trial():
+    """An untrained network attached to the handle: the first reduced solves
+    alternate between leaving it out and letting the judge consider it, and
+    after 8 solves per arm it is retired unless its solves took at least
+    half an iteration fewer.  An untrained network cannot do that; afterwards
+    no candidates are tried, and every solve still matches the direct one."""
+    torch = torch_cuda()
+    from paper_1008_1700_amd import ddps
+    d = configs.small_banded(6, [300, 340, 280, 330, 310, 290], 40, 21)
+    A = d["A"]
+    S = ddps.Solver(A, d["part_ptr"], dtype="bf16x3", inner_tol=1e-8, outer="refine", max_rhs=4)
+    m, t, _ = ddps.ddps_reduced_layout(S.h)
+    net = ddps.ddps_mlp_create(4 * t + 2, 32, 2 * t, 4 * (S.p - 1), seed=7, stream=S.stream.cuda_stream)
+    try:
+        S.factor()
+        ddps.ddps_set_guess_model(S.h, net)
+        tr0 = ddps.ddps_guess_trial(S.h)
+        assert tr0["state"] == "running" and tr0["solves_with"] == 0 and tr0["solves_without"] == 0
+        rng = np.random.default_rng(8)
+        for rep in range(4):
+            Xs = rng.uniform(-1, 1, (A.n, 4))
+            F = torch.from_numpy(np.ascontiguousarray((A.scipy() @ Xs).T)).cuda()
+            X = torch.zeros_like(F)
+            rc, info = ddps.ddps_solve_many(S.h, F, X, 1e-11)
+            assert rc == 0 and info.relres_inf <= 1e-11
+            assert relerr(host(X).T, Xs) <= 1e-8
+        tr = ddps.ddps_guess_trial(S.h)
+        print(f"trial: {tr}")
+        assert tr["state"] == "retired"
+        assert tr["solves_with"] >= 8 and tr["solves_without"] >= 8
+        assert tr["mean_iters_with"] > tr["mean_iters_without"] - 0.5
+        c0 = ddps.ddps_guess_counts(S.h)
+        X = torch.zeros_like(F)
+        rc, info = ddps.ddps_solve_many(S.h, F, X, 1e-11)
+        c1 = ddps.ddps_guess_counts(S.h)
+        assert c1["retired"] - c0["retired"] == 4 * info.applications
+        assert c1["learned"] == c0["learned"] and c1["zero"] == c0["zero"] and c1["ghat"] == c0["ghat"]
+    finally:
+        ddps.ddps_set_guess_model(S.h, None)
+        S.close()
+        ddps.ddps_mlp_destroy(net)

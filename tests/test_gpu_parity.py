@@ -445,3 +445,52 @@ def test_loosened_refinement_steps(c1, ratio):
             assert info.loosened_steps >= 1 and info.undone_steps <= 1
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("retrieval", [0, 1])
+def test_many_rhs_fp32_products_on_matrix_cores(retrieval):
+    """FP32 storage with 8 right-hand sides: the reduced products (and with
+    retrieval 0 the spike retrieval) run on the FP32 matrix cores with FP32
+    sums (gemv_sums 0, the default) or on the vector units with FP64 sums
+    (gemv_sums 1).  t = 256, so each tip block has 512 columns: the products'
+    main loop and its tail both run.  The two forms agree to the FP32
+    rounding of the sums, the FP64-sum form matches the oracle's reduced
+    product on c to the FP32 rounding of the spikes, and full solves of both
+    forms meet the 1e-12 residual and the direct solution."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    d = configs.small_banded(4, [600, 652, 700, 620], 200, 5)   # row counts multiples of 4: aligned spike rows
+    A = d["A"]
+    P = oracle_prec(d)
+    Ss = [make_solver(d, dtype="f32", inner_tol=1e-10, max_rhs=8, retrieval=retrieval, work_slots=2, gemv_sums=g)
+          for g in (0, 1)]
+    try:
+        for S in Ss:
+            S.factor()
+        m, t, _ = ddps.ddps_reduced_layout(Ss[0].h)
+        assert t == 256
+        c = torch.empty(m, dtype=torch.int64, device="cuda")
+        mask = torch.empty(m, dtype=torch.float64, device="cuda")
+        ddps.ddps_reduced_layout(Ss[0].h, c, mask)
+        on = host(mask) > 0
+        assert np.array_equal(host(c)[on], P.c)
+        X = np.random.default_rng(21).standard_normal((8, m)) * on
+        V = []
+        for S in Ss:
+            v = torch.empty(8, m, dtype=torch.float64, device="cuda")
+            ddps.ddps_reduced_matvec(S.h, 8, dev_vec(X), v)
+            V.append(host(v))
+        assert not np.array_equal(V[0], V[1])             # two arithmetic paths
+        assert maxrel(V[0], V[1]) <= 1e-5
+        for j in range(8):
+            assert maxrel(V[1][j][on], P.ghat_matvec(X[j][on])) <= 1e-4
+        Xs = np.random.default_rng(22).uniform(-1, 1, (8, A.n))
+        F = np.stack([A.scipy() @ x for x in Xs])
+        for S in Ss:
+            Xd = torch.zeros(8, A.n, dtype=torch.float64, device="cuda")
+            rc, info = ddps.ddps_solve_many(S.h, dev_vec(F), Xd, 1e-12)
+            assert rc == 0 and info.relres_inf <= 1e-12
+            assert relerr(host(Xd), Xs) <= 1e-9
+    finally:
+        for S in Ss:
+            S.close()

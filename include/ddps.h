@@ -458,6 +458,39 @@ int ddps_guess_counts(ddps_handle h, int64_t* counts);
  * the trial or by 8 lost reduced solves in a row).  Errors: DDPS_E_ARG. */
 int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t* state);
 
+/* ---------------------------------------------------------------- general
+ * sparse matrices.  The paper partitions general sparse matrices after a
+ * fill-reducing / bandwidth-reducing reordering (Section 3; it uses METIS);
+ * this path needs banded blocks, so a general matrix is first reordered by
+ * reverse Cuthill-McKee (Cuthill & McKee 1969; George & Liu 1981), which
+ * makes the profile of A + A^T narrow, and then cut into equal row slabs.
+ * All arrays here are host arrays; nothing touches the GPU. */
+
+/* Reverse Cuthill-McKee ordering of the symmetric pattern of A + A^T (CSR,
+ * n rows, int64 row_ptr[n+1], int32 col[nnz]; the diagonal is ignored).
+ * Each connected component starts from a pseudo-peripheral node (George-Liu
+ * search from a node of minimum degree); neighbours are visited in
+ * increasing degree, ties by index; the whole order is reversed.  perm[i] =
+ * the original index of new row i (int64[n], written).  Errors: DDPS_E_ARG
+ * (n < 0, null pointers for n > 0, a column outside [0, n)). */
+int ddps_rcm(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t* perm);
+
+/* Half-bandwidth b = max |i - j| over the stored entries (int64, written). */
+int ddps_bandwidth(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t* b);
+
+/* B = P A P^T for perm from ddps_rcm (new row i = old row perm[i]):
+ * out_row_ptr[n+1], out_col[nnz], out_val[nnz] written, columns sorted
+ * ascending within each row.  val / out_val may be null (pattern only). */
+int ddps_permute_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                     const int64_t* perm, int64_t* out_row_ptr, int32_t* out_col, double* out_val);
+
+/* Row partition of a matrix with half-bandwidth b into at most p_max equal
+ * slabs (sizes differing by at most one row) such that every slab has at
+ * least 2t rows, t = b rounded up to a multiple of 64 (what ddps_setup
+ * requires).  part_ptr (int64[p_max + 1]) and *p (the slabs used, >= 1) are
+ * written.  Errors: DDPS_E_ARG (p_max < 1, n < 1, b < 0). */
+int ddps_partition_rows(int64_t n, int64_t b, int32_t p_max, int64_t* part_ptr, int32_t* p);
+
 /* Device bytes held by the handle (host pointer). */
 int ddps_memory(ddps_handle h, size_t* bytes);
 
@@ -466,6 +499,11 @@ void ddps_destroy(ddps_handle h);
 
 /* Static string for a status code. */
 const char* ddps_status_string(int s);
+
+/* After DDPS_E_HIP: the HIP runtime's description of the error that caused
+ * it (the one recorded by the failing call, else the runtime's last error of
+ * this thread), then cleared.  A static string. */
+const char* ddps_last_hip_error(void);
 
 #ifdef __cplusplus
 }

@@ -1601,6 +1601,13 @@ void ddps_default_options(ddps_options* o) {
   o->gemv_sums = 0;
 }
 
+const char* ddps_last_hip_error(void) {
+  hipError_t e = last_hip_error();
+  if (e == hipSuccess) e = hipGetLastError();
+  last_hip_error() = hipSuccess;
+  return hipGetErrorString(e);
+}
+
 const char* ddps_status_string(int s) {
   switch (s) {
     case DDPS_OK: return "DDPS_OK";

@@ -124,6 +124,11 @@ _SIGS = {
     "ddps_set_guess_model": (_I32, [_P, _P]),
     "ddps_guess_counts": (_I32, [_P, ctypes.POINTER(_I64)]),
     "ddps_guess_trial": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
+    "ddps_rcm": (_I32, [_I64, _P, _P, _P]),
+    "ddps_last_hip_error": (ctypes.c_char_p, []),
+    "ddps_bandwidth": (_I32, [_I64, _P, _P, ctypes.POINTER(_I64)]),
+    "ddps_permute_csr": (_I32, [_I64, _P, _P, _P, _P, _P, _P, _P]),
+    "ddps_partition_rows": (_I32, [_I64, _I64, _I32, _P, ctypes.POINTER(_I32)]),
     "ddps_residual_norms": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D), _P]),
     "ddps_residual_norms_noalloc": (_I32, [_I64, _I32, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(_D),
                                            _P]),
@@ -138,6 +143,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1008_1700_amd.build")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so that one runtime (one device context) serves both, in
+        # whatever order the caller touches them
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -153,6 +162,8 @@ def exported_symbols():
 
 def _chk(code, where):
     if code != 0:
+        if STATUS.get(code) == "DDPS_E_HIP":
+            where = f"{where} ({lib().ddps_last_hip_error().decode()})"
         raise DDPSError(code, where)
 
 
@@ -403,6 +414,75 @@ def ddps_guess_trial(h):
     _chk(lib().ddps_guess_trial(h, n, mean, ctypes.byref(st)), "ddps_guess_trial")
     return dict(solves_without=n[0], solves_with=n[1], mean_iters_without=mean[0], mean_iters_with=mean[1],
                 state={0: "running", 1: "kept", 2: "retired"}[st.value])
+
+
+def _host(a, dtype):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def ddps_rcm(n, row_ptr, col):
+    """Reverse Cuthill-McKee permutation (host arrays): new row i = old row perm[i]."""
+    import numpy as np
+    rp, c = _host(row_ptr, np.int64), _host(col, np.int32)
+    perm = np.empty(n, dtype=np.int64)
+    _chk(lib().ddps_rcm(int(n), rp.ctypes.data, c.ctypes.data, perm.ctypes.data), "ddps_rcm")
+    return perm
+
+
+def ddps_bandwidth(n, row_ptr, col):
+    import numpy as np
+    rp, c = _host(row_ptr, np.int64), _host(col, np.int32)
+    b = _I64()
+    _chk(lib().ddps_bandwidth(int(n), rp.ctypes.data, c.ctypes.data, ctypes.byref(b)), "ddps_bandwidth")
+    return b.value
+
+
+def ddps_permute_csr(n, row_ptr, col, val, perm):
+    """B = P A P^T (host arrays); returns (row_ptr, col, val) of B."""
+    import numpy as np
+    rp, c, p = _host(row_ptr, np.int64), _host(col, np.int32), _host(perm, np.int64)
+    v = None if val is None else _host(val, np.float64)
+    orp = np.empty(n + 1, dtype=np.int64)
+    oc = np.empty(len(c), dtype=np.int32)
+    ov = None if v is None else np.empty(len(v), dtype=np.float64)
+    _chk(lib().ddps_permute_csr(int(n), rp.ctypes.data, c.ctypes.data, None if v is None else v.ctypes.data,
+                                p.ctypes.data, orp.ctypes.data, oc.ctypes.data, None if ov is None else ov.ctypes.data),
+         "ddps_permute_csr")
+    return orp, oc, ov
+
+
+def ddps_partition_rows(n, b, p_max):
+    import numpy as np
+    part = np.empty(int(p_max) + 1, dtype=np.int64)
+    p = _I32()
+    _chk(lib().ddps_partition_rows(int(n), int(b), int(p_max), part.ctypes.data, ctypes.byref(p)),
+         "ddps_partition_rows")
+    return part[:p.value + 1].copy()
+
+
+class GeneralSystem:
+    """A general sparse matrix prepared for the banded block path: reverse
+    Cuthill-McKee order, the permuted CSR (attributes n, row_ptr, col, val,
+    as Solver takes them), its half-bandwidth and an equal-slab partition
+    into at most p_max blocks.  to_perm / from_perm move vectors between the
+    original and the permuted numbering."""
+
+    def __init__(self, n, row_ptr, col, val, p_max):
+        self.perm = ddps_rcm(n, row_ptr, col)
+        self.n = int(n)
+        self.row_ptr, self.col, self.val = ddps_permute_csr(n, row_ptr, col, val, self.perm)
+        self.b = ddps_bandwidth(n, self.row_ptr, self.col)
+        self.part_ptr = ddps_partition_rows(n, self.b, p_max)
+
+    def to_perm(self, x):
+        return x[self.perm]
+
+    def from_perm(self, y):
+        import numpy as np
+        out = np.empty_like(y)
+        out[self.perm] = y
+        return out
 
 
 def ddps_memory(h):

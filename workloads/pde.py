@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "CSR", "stencil_csr", "convdiff2d", "convdiff3d", "aniso_diffusion2d",
     "vardiff_reaction3d", "implicit_euler_convdiff2d", "slab_partition",
-    "uneven_partition", "random_banded", "csr_matvec", "csr_to_dense",
+    "uneven_partition", "random_banded", "random_geometric", "csr_matvec", "csr_to_dense",
 ]
 
 
@@ -250,3 +250,30 @@ def random_banded(n, b, seed, density=0.6, margin=0.5, nonsym=True):
     dmask = rows == A.col.astype(np.int64)
     val[dmask] = d[rows[dmask]]
     return CSR(n, A.row_ptr, A.col, val)
+
+
+def random_geometric(n, degree, seed, shuffle=True):
+    """A general (non-banded) sparse system: n points uniform in the unit
+    square, each joined to the points within the radius that gives about
+    `degree` neighbours on average; off-diagonal entries -(0.5 + u) with u ~
+    U[0,1) independently for a_ij and a_ji (nonsymmetric), diagonal = the
+    larger of the absolute row and column sums + 0.5 + U[0,1): a strictly
+    row- and column-diagonally-dominant M-matrix.  The rows come in a random
+    order (shuffle) or sorted by x, then y."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    if not shuffle:
+        pts = pts[np.lexsort((pts[:, 1], pts[:, 0]))]
+    radius = np.sqrt(degree / (np.pi * n))
+    pairs = cKDTree(pts).query_pairs(radius, output_type="ndarray")
+    i = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    j = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    v = -(0.5 + rng.random(len(i)))
+    import scipy.sparse as sp
+    M = sp.csr_matrix((v, (i, j)), shape=(n, n))
+    rs = np.asarray(abs(M).sum(axis=1)).ravel()
+    cs = np.asarray(abs(M).sum(axis=0)).ravel()
+    M = (M + sp.diags(np.maximum(rs, cs) + 0.5 + rng.random(n))).tocsr()
+    M.sort_indices()
+    return CSR(n, M.indptr, M.indices, M.data)

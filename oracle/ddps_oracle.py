@@ -10,6 +10,7 @@ kernels are checked.
 Stages (Section 3, Figures 1 and 2):
   1  split A = D + R by the given row partition              -> split()
   2  LU of every diagonal block A_ii (exact, banded LAPACK)   -> factor_block()
+     or its incomplete LU with zero fill (L~_i U~_i)           -> factor_block_ilu0()
   3  drop columns of R_i with the delta rule                  -> kept_columns()
   4  spikes G_i = A_ii^{-1} R~_i(:, c_i)                      -> Preconditioner
   5  c = indices of the nonzero columns of G (ascending)      -> Preconditioner
@@ -37,6 +38,10 @@ Readings of the paper taken here (each is listed in the design notes):
     M-matrices, for which no row interchange happens, so there the factors
     are the unique unpivoted LU factors; factor_block(require_no_pivot=True)
     checks that before factors are compared entry by entry.
+  * the incomplete factors of Section 3 (A~_ii = L~_i U~_i, the kind left
+    open there) are read as ILU(0): L~_i unit lower and U~_i upper with the
+    sparsity pattern of A_ii, so that (L~_i U~_i)(j,k) = a_jk wherever A_ii
+    stores an entry; no pivoting, every row must store its diagonal.
 """
 from __future__ import annotations
 
@@ -149,6 +154,71 @@ def block_solve(fac: BandLU, Y):
     X, info = lapack.dgbtrs(fac.lu, fac.kl, fac.ku, Y2, fac.ipiv)
     assert info == 0
     return X.ravel() if vec else X
+
+
+# --------------------------------------------------------------------------
+# Stage 2 with incomplete factors (Section 3: D~ built from L~_i U~_i).
+# --------------------------------------------------------------------------
+@dataclass
+class ILU0:
+    L: sp.csr_matrix   # unit lower triangular (ones stored on the diagonal)
+    U: sp.csr_matrix   # upper triangular, the pivots on its diagonal
+    n: int
+
+
+def factor_block_ilu0(Aii):
+    """ILU(0) of A_ii: Gaussian elimination row by row (the IKJ order of
+    Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Sec. 10.3.2)
+    in which every update that would land outside the pattern of A_ii is
+    discarded.  Row i, for each k < i that it stores, in increasing order:
+    l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for each j > k stored in both
+    row i and the finished row k.  Plain Python over the stored entries."""
+    A = sp.csr_matrix(Aii, dtype=np.float64)
+    A.sum_duplicates()
+    A.sort_indices()
+    n = A.shape[0]
+    done = []                                  # finished rows: {col: value}
+    for i in range(n):
+        a, b = A.indptr[i], A.indptr[i + 1]
+        row = {int(j): float(v) for j, v in zip(A.indices[a:b], A.data[a:b])}
+        if i not in row:
+            raise np.linalg.LinAlgError(f"row {i} stores no diagonal entry")
+        for k in sorted(j for j in row if j < i):
+            ukk = done[k][k]
+            if ukk == 0.0:
+                raise np.linalg.LinAlgError(f"zero pivot in row {k}")
+            row[k] /= ukk
+            lik = row[k]
+            for j, ukj in done[k].items():
+                if j > k and j in row:
+                    row[j] -= lik * ukj
+        if row[i] == 0.0:
+            raise np.linalg.LinAlgError(f"zero pivot in row {i}")
+        done.append(row)
+    li, lj, lv, ui, uj, uv = [], [], [], [], [], []
+    for i, row in enumerate(done):
+        li.append(i); lj.append(i); lv.append(1.0)
+        for j, v in row.items():
+            if j < i:
+                li.append(i); lj.append(j); lv.append(v)
+            else:
+                ui.append(i); uj.append(j); uv.append(v)
+    L = sp.csr_matrix((lv, (li, lj)), shape=(n, n))
+    U = sp.csr_matrix((uv, (ui, uj)), shape=(n, n))
+    return ILU0(L, U, n)
+
+
+def ilu0_solve(fac: ILU0, Y):
+    """(L~ U~)^{-1} Y by the two sparse triangular solves."""
+    import scipy.sparse.linalg as spla
+    Y = np.asarray(Y, dtype=np.float64)
+    W = spla.spsolve_triangular(fac.L, Y, lower=True, unit_diagonal=True)
+    return spla.spsolve_triangular(fac.U, W, lower=False)
+
+
+def solve_with(fac, Y):
+    """D~_ii^{-1} Y for either kind of block factor."""
+    return ilu0_solve(fac, Y) if isinstance(fac, ILU0) else block_solve(fac, Y)
 
 
 def unit_lower_and_upper(fac: BandLU):
@@ -272,16 +342,19 @@ def bicgstab(matvec, b, x0=None, tol=1e-10, maxit=1000, precond=None,
 class Preconditioner:
     """Stages 1-5 of Figure 1 (no right-hand side needed) and P z = y."""
 
-    def __init__(self, n, row_ptr, col, val, part_ptr, delta=0.0):
+    def __init__(self, n, row_ptr, col, val, part_ptr, delta=0.0, block_factor="lu"):
         self.n = int(n)
         self.part_ptr = np.asarray(part_ptr, dtype=np.int64)
         self.A, self.blocks = split(n, row_ptr, col, val, self.part_ptr)      # stage 1
-        self.factors = [factor_block(b.Aii) for b in self.blocks]              # stage 2
+        if block_factor not in ("lu", "ilu0"):
+            raise ValueError(block_factor)
+        fac = factor_block if block_factor == "lu" else factor_block_ilu0
+        self.factors = [fac(b.Aii) for b in self.blocks]                       # stage 2
         self.c_i = [kept_columns(b.Ri, delta) for b in self.blocks]            # stage 3
         self.G = []                                                            # stage 4
         for b, fac, ci in zip(self.blocks, self.factors, self.c_i):
             Rt = b.Ri[:, ci].toarray() if ci.size else np.zeros((b.hi - b.lo, 0))
-            self.G.append(block_solve(fac, Rt) if ci.size else Rt)
+            self.G.append(solve_with(fac, Rt) if ci.size else Rt)
         nz = [ci[np.any(Gi != 0.0, axis=0)] if ci.size else ci                 # stage 5
               for ci, Gi in zip(self.c_i, self.G)]
         self.c = np.unique(np.concatenate(nz)) if nz else np.zeros(0, np.int64)
@@ -354,7 +427,7 @@ class Preconditioner:
         y = np.asarray(y, dtype=np.float64)
         g = np.empty(self.n)
         for b, fac in zip(self.blocks, self.factors):                         # 6.1
-            g[b.lo:b.hi] = block_solve(fac, y[b.lo:b.hi])
+            g[b.lo:b.hi] = solve_with(fac, y[b.lo:b.hi])
         gh = g[self.c]                                                        # 6.2
         inner = KrylovInfo(converged=True, relres=0.0)
         if self.m == 0:
@@ -373,7 +446,7 @@ class Preconditioner:
             z = np.empty(self.n)
             for b, fac, ci in zip(self.blocks, self.factors, self.c_i):       # 6.5, re-solved
                 rhs = y[b.lo:b.hi] - (b.Ri[:, ci] @ zfull[ci] if ci.size else 0.0)
-                z[b.lo:b.hi] = block_solve(fac, rhs)
+                z[b.lo:b.hi] = solve_with(fac, rhs)
         else:
             raise ValueError(retrieval)
         return z, dict(g=g, ghat=gh, zhat=zh, inner=inner)
@@ -394,11 +467,11 @@ class SolveInfo:
 
 def solve(n, row_ptr, col, val, part_ptr, f, delta=0.0, tol=1e-10, outer="refine",
           outer_maxit=1000, reduced="dense", inner_tol=1e-12, inner_maxit=1000, prec=None,
-          retrieval="spikes", norm="inf"):
+          retrieval="spikes", norm="inf", block_factor="lu"):
     """DDPS for Ax = f.  outer in {'none', 'refine', 'bicgstab'}; the outer
     stopping test is ||f - Ax|| / ||f|| <= tol in the norm `norm` ('inf',
     the paper's choice in Section 4, or '2')."""
-    P = prec if prec is not None else Preconditioner(n, row_ptr, col, val, part_ptr, delta)
+    P = prec if prec is not None else Preconditioner(n, row_ptr, col, val, part_ptr, delta, block_factor)
     A = P.A
     f = np.asarray(f, dtype=np.float64)
     info = SolveInfo()

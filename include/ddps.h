@@ -120,6 +120,18 @@ typedef struct {
                               with FP32 sums on the matrix cores (default), 1 = FP64 sums on
                               the vector units.  Either way the sums of four column ranges are
                               added in FP64, and vectors, dots and residuals stay FP64 */
+  int32_t block_factor;    /* stage 2 of Figure 1: 0 = exact LU of every A_ii (unpivoted, in
+                              t x t band tiles); 1 = incomplete factors A~_ii = L~_i U~_i
+                              (Section 3), read as ILU(0): L~_i unit lower and U~_i upper
+                              with the sparsity pattern of A_ii and (L~_i U~_i)(r, j) = a_rj
+                              wherever A_ii stores an entry.  Factors in FP64 at A's CSR
+                              positions; the spikes D~^{-1} R~ come from sparse triangular
+                              solves in the storage type of factor_dtype (FP64 for DDPS_F64,
+                              else FP32) and only their tips are kept, so p > 1 requires
+                              retrieval = 1 (DDPS_E_ARG otherwise).  Every row must store its
+                              diagonal entry and its columns sorted without repeats
+                              (DDPS_E_ARG otherwise).  ddps_get_tile, ddps_set_execution
+                              and ddps_autotune then return DDPS_E_STATE */
 } ddps_options;
 
 typedef struct {
@@ -142,7 +154,7 @@ typedef struct {
  * max_rhs 1, no memory budget, null stream, automatic stream groups, no
  * graph, no inner preconditioner, spikes kept in full (retrieval 0),
  * inf-norm stopping test, automatic workspace slots, BiCGStab reduced
- * solve. */
+ * solve, FP32 sums on the matrix cores, exact block factors. */
 void ddps_default_options(ddps_options* opt);
 
 /* Stages 1, 3 and 5 (Section 3, Figure 1): split A = D + R for the row

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libddps.so")
 SOURCES = ["k_gemm.hip", "k_panel.hip", "k_gemv.hip", "k_setup.hip", "k_vec.hip", "k_mlp.hip", "ddps.cpp", "mlp.cpp",
-           "noalloc.hip", "reorder.cpp"]
+           "noalloc.hip", "reorder.cpp", "k_ilu.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -115,6 +115,19 @@ struct ddps_ctx {
   std::vector<Launch> sch_rfac, sch_rsol;
   std::vector<SumRec> sums;   // records of the LK_SUM launches
   void* d_tipcm = nullptr;   // 2(p-1) tip parts, t x 2t column-major (ld t), part 2i-1 / 2i as in d_tips
+  // Incomplete block factors (block_factor = 1): ILU(0) values at A's CSR
+  // positions (d_fv), per row the positions of its lower part, pivot and
+  // end (d_ilo, d_idg, d_ihi), the forward and backward level lists, and
+  // the spike workspace of nslots blocks (ilu_nmax x 2t, row-major each);
+  // ilu_batches lists the blocks batch after batch (d_ibatch, same order)
+  bool ilu = false;
+  double* d_fv = nullptr;
+  int64_t *d_ilo = nullptr, *d_idg = nullptr, *d_ihi = nullptr, *d_lptr = nullptr, *d_uptr = nullptr;
+  int32_t *d_lrows = nullptr, *d_urows = nullptr, *d_ibatch = nullptr;
+  IluBlock* d_iblk = nullptr;
+  void* d_iws = nullptr;
+  int64_t ilu_nmax = 0, ilu_nnz = 0, ilu_levels = 0;
+  std::vector<std::pair<int, int>> ilu_batches;   // (first entry in d_ibatch, blocks)
   int R = 1;
   // device data
   int64_t *d_part = nullptr, *d_rowptr = nullptr;
@@ -899,7 +912,8 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
   const double eb = (double)h->elt;
   double* yp = h->d_ypad;
   double* vp = h->d_vpad;
-  for (int k = 0; k < h->Tmax; ++k) {
+  // (incomplete factors: the block solves are level-scheduled kernels, no tile sweeps)
+  for (int k = 0; k < (h->ilu ? 0 : h->Tmax); ++k) {
     sb.begin(LK_GEMV);
     for (int i = 0; i < p; ++i) {
       const BlockInfo& B = h->blk[i];
@@ -940,7 +954,7 @@ void build_solve_schedules(ddps_ctx* h, ScheduleBuilder& sb) {
     }
     sb.end(h->sch_fwd);
   }
-  for (int s = 0; s < h->Tmax; ++s) {
+  for (int s = 0; s < (h->ilu ? 0 : h->Tmax); ++s) {
     sb.begin(LK_GEMV);
     for (int i = 0; i < p; ++i) {
       const BlockInfo& B = h->blk[i];
@@ -1145,9 +1159,28 @@ int run_schedule(ddps_ctx* h, const std::vector<Launch>& S, int R, int64_t ldx, 
   return run_schedule(h, S, R, ldx, ldy, tk_gemv, h->stream);
 }
 
+// Stages 2 and 4 with incomplete factors: ILU(0) of every block, then the
+// spikes batch by batch (only their tips kept), then the direct reduced
+// solve's factorisation if asked for.
+int enqueue_factor_ilu(ddps_ctx* h) {
+  hipStream_t f = h->fstream;
+  int rc = do_scatter(h, f);
+  if (rc) return rc;
+  ilu_factor(h->p, h->d_iblk, h->d_lrows, h->d_lptr, h->d_ilo, h->d_idg, h->d_ihi, h->d_col, h->d_val, h->d_fv,
+             h->d_thresh, h->d_bad, f);
+  if (h->tips_only)
+    for (const auto& b : h->ilu_batches)
+      ilu_spikes(h->sdt, b.second, h->d_iblk, h->d_ibatch + b.first, h->p, h->t, h->d_rhs, h->d_ilo, h->d_idg,
+                 h->d_ihi, h->d_col, h->d_fv, h->d_iws, h->ilu_nmax * 2 * h->t, h->d_tipcm, f);
+  if ((rc = run_schedule(h, h->sch_rfac, 1, 0, 0, TK_GEMM, f, TK_RFAC))) return rc;
+  HIPCHK(hipGetLastError());
+  return DDPS_OK;
+}
+
 // Stages 1-5 on the internal factor stream: scatter, then every group's
 // schedule on its own stream (fork/join through events).
 int enqueue_factor(ddps_ctx* h) {
+  if (h->ilu) return enqueue_factor_ilu(h);
   hipStream_t f = h->fstream;
   int rc = do_scatter(h, f);
   if (rc) return rc;
@@ -1203,7 +1236,10 @@ int build_schedules(ddps_ctx* h) {
   h->mode_cursor = 0;
   h->sch_group.assign(G, {});
   h->wslot.assign(p, 0);
-  if (!h->tips_only) {
+  if (h->ilu) {
+    // incomplete factors: no factor schedule (the factor kernels run per
+    // batch of ilu_batches), only the solve-phase launches below
+  } else if (!h->tips_only) {
     for (int i = 0; i < p; ++i) h->wslot[i] = i;
     for (int g = 0; g < G; ++g) {
       std::vector<int> mem;
@@ -1277,6 +1313,26 @@ int build_schedules(ddps_ctx* h) {
   }
   h->drop_graph();
   if ((int64_t)h->W1 * h->R * 2 > h->part_cap) return DDPS_E_ARG;
+  return DDPS_OK;
+}
+
+// Step 6.1 on the padded vector d_ypad, in place (R columns): the tile
+// sweeps of the exact factors, or the level-scheduled triangular solves of
+// the incomplete ones.
+int block_solves(ddps_ctx* h, int tk) {
+  const int R = h->R;
+  if (!h->ilu) {
+    int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, tk);
+    if (rc) return rc;
+    return run_schedule(h, h->sch_bwd, R, h->Np, h->Np, tk);
+  }
+  hipEvent_t a;
+  h->tim_begin(tk, a);
+  ilu_solve(h->p, h->d_iblk, h->d_lrows, h->d_lptr, h->d_urows, h->d_uptr, h->d_ilo, h->d_idg, h->d_ihi, h->d_col,
+            h->d_fv, h->d_ypad, h->Np, R, h->stream);
+  // both triangles once (values and column indices), each vector entry read and written per sweep
+  h->tim_end(tk, a, 2.0 * (double)h->ilu_nnz * R, 12.0 * (double)h->ilu_nnz + 32.0 * (double)h->n * R);
+  HIPCHK(hipGetLastError());
   return DDPS_OK;
 }
 
@@ -1442,9 +1498,7 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
   const int R = h->R;
   hipStream_t s = h->stream;
   vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, ldy, h->d_ypad, s);
-  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
-  if (rc) return rc;
-  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  int rc = block_solves(h, TK_SWEEP);
   if (rc) return rc;
   vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_gh, s);
   if (h->gnet && h->m > 0 && h->sch_rsol.empty()) {
@@ -1491,9 +1545,7 @@ int prec_apply(ddps_ctx* h, int k, const double* y, int64_t ldy, double* z, int6
     // 6.5 re-solved: z = D~^{-1}(y - R~ z^), the block sweeps once more
     coupling_rhs(h->Np, R, k, h->p, h->t, h->d_blk, h->d_rowptr, h->d_col, h->d_val, y, ldy, h->d_zh, h->m,
                  h->d_mask, h->d_ypad, s);
-    rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_RETR);
-    if (rc) return rc;
-    rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_RETR);
+    rc = block_solves(h, TK_RETR);
     if (rc) return rc;
     vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_ypad, z, ldz, s);
   } else {
@@ -1599,6 +1651,7 @@ void ddps_default_options(ddps_options* o) {
   o->reduced_solve = 0;
   o->loosen_ratio = 0.0;
   o->gemv_sums = 0;
+  o->block_factor = 0;
 }
 
 const char* ddps_last_hip_error(void) {
@@ -1649,6 +1702,130 @@ void ddps_destroy(ddps_handle h) {
   delete h;
 }
 
+namespace {
+
+// Host plan of the incomplete-factor form: per row the CSR positions of its
+// in-block lower part, pivot and end; each block's rows grouped into forward
+// levels (level of r = 1 + the largest level among its lower-pattern rows)
+// and backward levels (the same over the upper pattern); the block records.
+struct IluPlan {
+  std::vector<int64_t> lo, dg, hi, lptr, uptr;
+  std::vector<int32_t> lrows, urows;
+  std::vector<IluBlock> blk;
+};
+
+int ilu_plan(ddps_ctx* h, IluPlan& P) {
+  const int64_t n = h->n, nnz = h->nnz;
+  const int p = h->p;
+  std::vector<int64_t> rp(n + 1);
+  std::vector<int32_t> cl(nnz);
+  if (hipMemcpyAsync(rp.data(), h->d_rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(cl.data(), h->d_col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return DDPS_E_HIP;
+  P.lo.assign(n, 0);
+  P.dg.assign(n, -1);
+  P.hi.assign(n, 0);
+  P.lrows.assign(n, 0);
+  P.urows.assign(n, 0);
+  P.lptr.clear();
+  P.uptr.clear();
+  P.blk.assign(p, IluBlock{});
+  std::vector<int64_t> lev(n, 0), cnt;
+  h->ilu_nmax = 0;
+  h->ilu_nnz = 0;
+  h->ilu_levels = 0;
+  for (int i = 0; i < p; ++i) {
+    const BlockInfo& B = h->blk[i];
+    const int64_t s0 = B.s, s1 = B.s + B.n;
+    for (int64_t r = s0; r < s1; ++r) {
+      int64_t q = rp[r];
+      const int64_t e = rp[r + 1];
+      for (int64_t u = q + 1; u < e; ++u)
+        if (cl[u] <= cl[u - 1]) return DDPS_E_ARG;   // columns must be sorted, no repeats
+      while (q < e && cl[q] < s0) ++q;
+      P.lo[r] = q;
+      while (q < e && cl[q] < s1) {
+        if (cl[q] == r) P.dg[r] = q;
+        ++q;
+      }
+      P.hi[r] = q;
+      if (P.dg[r] < 0) return DDPS_E_ARG;   // no stored diagonal: a structurally zero pivot
+      h->ilu_nnz += P.hi[r] - P.lo[r];
+    }
+    h->ilu_nmax = std::max<int64_t>(h->ilu_nmax, B.n);
+    // levels over one triangle, rows visited in dependency order, then
+    // bucketed by level (a counting sort keeps the row order within a level)
+    auto levels = [&](bool fwd, std::vector<int32_t>& rows, std::vector<int64_t>& ptr, int64_t& beg,
+                      int64_t& num) {
+      int64_t top = 0;
+      for (int64_t k = 0; k < B.n; ++k) {
+        const int64_t r = fwd ? s0 + k : s1 - 1 - k;
+        int64_t lv = 0;
+        const int64_t a = fwd ? P.lo[r] : P.dg[r] + 1, e = fwd ? P.dg[r] : P.hi[r];
+        for (int64_t q = a; q < e; ++q) lv = std::max(lv, lev[cl[q]] + 1);
+        lev[r] = lv;
+        top = std::max(top, lv + 1);
+      }
+      cnt.assign(top + 1, 0);
+      for (int64_t r = s0; r < s1; ++r) ++cnt[lev[r] + 1];
+      for (int64_t l = 0; l < top; ++l) cnt[l + 1] += cnt[l];
+      beg = (int64_t)ptr.size();
+      num = top;
+      for (int64_t l = 0; l <= top; ++l) ptr.push_back(s0 + cnt[l]);
+      for (int64_t k = 0; k < B.n; ++k) {
+        const int64_t r = fwd ? s0 + k : s1 - 1 - k;
+        rows[s0 + cnt[lev[r]]++] = (int32_t)r;
+      }
+    };
+    IluBlock& I = P.blk[i];
+    I.s = s0;
+    I.n = B.n;
+    I.vbase = B.voff + B.pad;
+    I.left = i > 0;
+    I.right = i < p - 1;
+    levels(true, P.lrows, P.lptr, I.lbeg, I.lnum);
+    levels(false, P.urows, P.uptr, I.ubeg, I.unum);
+    h->ilu_levels = std::max<int64_t>(h->ilu_levels, I.lnum + I.unum);
+  }
+  return DDPS_OK;
+}
+
+size_t ilu_plan_bytes(const ddps_ctx* h, const IluPlan& P) {
+  return (size_t)h->nnz * 8 + (size_t)h->n * (3 * 8 + 2 * 4) + (P.lptr.size() + P.uptr.size()) * 8 +
+         (size_t)h->p * (sizeof(IluBlock) + 4);
+}
+
+int ilu_upload(ddps_ctx* h, const IluPlan& P) {
+  int rc;
+  const int64_t n = h->n, p = h->p;
+  if ((rc = h->alloc(h->d_fv, h->nnz)) || (rc = h->alloc(h->d_ilo, n)) || (rc = h->alloc(h->d_idg, n)) ||
+      (rc = h->alloc(h->d_ihi, n)) || (rc = h->alloc(h->d_lrows, n)) || (rc = h->alloc(h->d_urows, n)) ||
+      (rc = h->alloc(h->d_lptr, (int64_t)P.lptr.size())) || (rc = h->alloc(h->d_uptr, (int64_t)P.uptr.size())) ||
+      (rc = h->alloc(h->d_iblk, p)) || (rc = h->alloc(h->d_ibatch, p)))
+    return rc;
+  std::vector<int32_t> order(p);
+  for (int i = 0; i < p; ++i) order[i] = i;
+  hipStream_t s = h->stream;
+  HIPCHK(hipMemcpyAsync(h->d_ilo, P.lo.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_idg, P.dg.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_ihi, P.hi.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_lrows, P.lrows.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_urows, P.urows.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_lptr, P.lptr.data(), sizeof(int64_t) * P.lptr.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_uptr, P.uptr.data(), sizeof(int64_t) * P.uptr.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_iblk, P.blk.data(), sizeof(IluBlock) * p, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_ibatch, order.data(), sizeof(int32_t) * p, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h->ilu_batches.clear();
+  const int64_t per = std::max<int64_t>(1, h->nslots);
+  for (int64_t b0 = 0; b0 < p; b0 += per) h->ilu_batches.push_back({(int)b0, (int)std::min<int64_t>(per, p - b0)});
+  return DDPS_OK;
+}
+
+}  // namespace
+
 int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, const int64_t* row_ptr,
                const int32_t* col, const double* val, int64_t nnz, const ddps_options* opt) {
   if (!out) return DDPS_E_ARG;
@@ -1673,7 +1850,8 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
       o.outer_maxit < 1 || o.max_rhs < 1 || o.max_rhs > kMaxRhs || !(o.inner_tol > 0.0) || o.inner_prec < 0 ||
       o.inner_prec > 1 || o.retrieval < 0 || o.retrieval > 1 || (o.norm != 0 && o.norm != 2) || o.work_slots < 0 ||
       o.reduced_solve < 0 || o.reduced_solve > 1 || std::isnan(o.loosen_ratio) || o.gemv_sums < 0 ||
-      o.gemv_sums > 1) {
+      o.gemv_sums > 1 || o.block_factor < 0 || o.block_factor > 1 ||
+      (o.block_factor == 1 && p > 1 && o.retrieval != 1)) {
     delete h;
     return DDPS_E_ARG;
   }
@@ -1747,11 +1925,14 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     h->Tmax = std::max<int>(h->Tmax, (int)B.T);
     h->Nmax = std::max<int64_t>(h->Nmax, B.N);
   }
-  h->tile_elems = tiles;
+  h->ilu = o.block_factor == 1;
+  h->tile_elems = h->ilu ? 0 : tiles;
   h->tips_only = o.retrieval == 1 && p > 1;
   h->Np = voff;
   h->m = p > 1 ? (int64_t)2 * t * (p - 1) : 0;
-  h->scr_per_block = ddps_ctx::scratch_elems(t);
+  h->scr_per_block = h->ilu ? 0 : ddps_ctx::scratch_elems(t);
+  IluPlan iplan;
+  if (h->ilu && (rc = ilu_plan(h, iplan))) return fail(rc);
   h->groups = o.factor_streams > 0 ? o.factor_streams : default_groups(h);
   // memory plan (F1 check before the large allocations)
   const int R = h->R;
@@ -1773,6 +1954,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   need += (size_t)m * R * 8 * 11;
   need += (size_t)n * R * 8 * 10;
   need += (size_t)Wmax * R * 4 * 8;
+  if (h->ilu) need += ilu_plan_bytes(h, iplan);
   size_t budget = o.mem_budget;
   if (budget == 0) {
     size_t fr = 0, tot = 0;
@@ -1782,7 +1964,9 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   // workspace: a scratch area per block, and the whole spike array; with the
   // tips only, `nslots` slots of scratch + an Nmax x 2t spike matrix, as many
   // as the budget allows (at most p, or opt.work_slots)
-  const size_t slot_bytes = (size_t)(h->scr_per_block + (p > 1 ? h->Nmax * 2 * t : 0)) * h->elt;
+  // (incomplete factors: a slot is one block's n x 2t spike workspace)
+  const size_t slot_bytes = h->ilu ? (size_t)h->ilu_nmax * 2 * t * h->elt
+                                   : (size_t)(h->scr_per_block + (p > 1 ? h->Nmax * 2 * t : 0)) * h->elt;
   if (!h->tips_only) {
     h->nslots = p;
     h->nspike = goff;
@@ -1799,9 +1983,10 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     if (fit < 1) return fail(DDPS_E_NOMEM);
     h->nslots = fit;
     h->groups = (int)std::min<int64_t>(h->groups, fit);
-    h->nspike = fit * h->Nmax * 2 * t;
+    h->nspike = h->ilu ? 0 : fit * h->Nmax * 2 * t;
     need += (size_t)fit * slot_bytes;
   }
+  if (h->ilu && !h->tips_only) h->nspike = 0;
   int64_t nlu = 0;
   h->lu_off.assign(p, 0);
   for (int i = 0; i < p; ++i) {
@@ -1809,7 +1994,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     nlu += (h->blk[i].T - 1) * h->pair_elems();
   }
   const size_t lu_bytes = (size_t)nlu * h->elt;
-  const bool sep_lu = nlu > 0 && need + lu_bytes <= budget;
+  const bool sep_lu = !h->ilu && nlu > 0 && need + lu_bytes <= budget;
   void* vp;
   if (sep_lu) {
     if ((rc = h->alloc_raw(vp, lu_bytes))) return fail(rc);
@@ -1823,6 +2008,14 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (h->tip_nseg > 0) {
     if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
     h->d_tips = vp;
+  }
+  if (h->ilu) {
+    if (h->tips_only) {
+      if ((rc = h->alloc_raw(vp, (size_t)h->nslots * h->ilu_nmax * 2 * t * h->elt))) return fail(rc);
+      h->d_iws = vp;
+    }
+    if ((rc = ilu_upload(h, iplan))) return fail(rc);
+    iplan = IluPlan();
   }
   if (h->tips_only) {
     if ((rc = h->alloc_raw(vp, (size_t)h->m * 2 * t * h->elt))) return fail(rc);
@@ -2340,9 +2533,7 @@ int ddps_block_solve(ddps_handle h, int32_t k, const double* y, double* g) {
   if (!h->factored) return DDPS_E_STATE;
   const int R = h->R;
   vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, h->n, h->d_ypad, h->stream);
-  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
-  if (rc) return rc;
-  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  int rc = block_solves(h, TK_SWEEP);
   if (rc) return rc;
   vec_from_padded(h->Np, k, h->p, h->d_blk, h->d_ypad, g, h->n, h->stream);
   HIPCHK(hipGetLastError());
@@ -2371,9 +2562,7 @@ int ddps_reduced_rhs(ddps_handle h, int32_t k, const double* y, double* ghat) {
   const int R = h->R;
   hipStream_t s = h->stream;
   vec_to_padded(h->Np, R, k, h->p, h->d_blk, y, h->n, h->d_ypad, s);
-  int rc = run_schedule(h, h->sch_fwd, R, h->Np, h->Np, TK_SWEEP);
-  if (rc) return rc;
-  rc = run_schedule(h, h->sch_bwd, R, h->Np, h->Np, TK_SWEEP);
+  int rc = block_solves(h, TK_SWEEP);
   if (rc) return rc;
   vec_gather_reduced(h->m, R, h->d_rrow, h->d_mask, h->d_ypad, h->Np, h->d_r, s);
   HIPCHK(hipMemcpyAsync(ghat, h->d_r, sizeof(double) * h->m * k, hipMemcpyDeviceToDevice, s));
@@ -2457,6 +2646,7 @@ int ddps_guess_target(ddps_handle h, int32_t k, const double* zhat, const double
 
 int ddps_get_tile(ddps_handle h, int32_t blk, int32_t k, int32_t which, double* dst) {
   if (!h || !dst || blk < 0 || blk >= h->p || which < 0 || which > 2) return DDPS_E_ARG;
+  if (h->ilu) return DDPS_E_STATE;   // incomplete factors keep no tiles
   const BlockInfo& B = h->blk[blk];
   if (k < 0 || k >= B.T || (which > 0 && k >= B.T - 1)) return DDPS_E_ARG;
   const int t = h->t;
@@ -2530,6 +2720,7 @@ int ddps_last_singular(ddps_handle h, int32_t* block, int64_t* row) {
 
 int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t tile_policy) {
   if (!h || streams < 0 || tile_policy < 0 || tile_policy > 5) return DDPS_E_ARG;
+  if (h->ilu) return DDPS_E_STATE;   // no factor schedule to arrange
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipStreamSynchronize(h->fstream));
   h->groups = streams > 0 ? streams : default_groups(h);
@@ -2708,6 +2899,7 @@ int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
 int ddps_autotune(ddps_handle h, const char* cache_path, double budget_s, int32_t* streams, int32_t* tile_policy,
                   double* factor_ms) {
   if (!h) return DDPS_E_ARG;
+  if (h->ilu) return DDPS_E_STATE;
   const std::string key = tune_key(h);
   const auto t0 = std::chrono::steady_clock::now();
   // once the budget is spent no further form is timed: the best one so far

@@ -109,6 +109,33 @@ struct BlockInfo {
   int64_t voff;
 };
 
+// ---------------------------------------------------------------- ILU(0) blocks
+// Block of the incomplete-factor form: global rows [s, s + n), the padded
+// vector index of row s (vbase), its forward levels (rows lrows[lptr[lbeg +
+// l] .. lptr[lbeg + l + 1]) for l < lnum) and backward levels (urows, uptr,
+// ubeg, unum), and whether it has a left / right coupling.
+struct IluBlock {
+  int64_t s, n, vbase;
+  int64_t lbeg, lnum, ubeg, unum;
+  int32_t left, right;
+};
+// ILU(0) of every block (values from val into fv at the CSR positions),
+// pivots checked against thresh (padded layout) into bad.
+void ilu_factor(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const int64_t* lo,
+                const int64_t* dg, const int64_t* hi, const int32_t* col, const double* val, double* fv,
+                const double* thresh, unsigned long long* bad, hipStream_t s);
+// Spike columns of the nb blocks listed in batch (block b in workspace slot
+// b: n x 2t row-major, slot_elems apart) from the compact coupling store
+// rhs, then their tips into the column-major tip store; dtype 0 double,
+// 1 float (rhs, ws and tips alike).
+void ilu_spikes(int dtype, int nb, const IluBlock* blocks, const int32_t* batch, int p, int t, const void* rhs,
+                const int64_t* lo, const int64_t* dg, const int64_t* hi, const int32_t* col, const double* fv,
+                void* ws, int64_t slot_elems, void* tips, hipStream_t s);
+// y = D~^{-1} y in place on the padded vector (R columns, stride ldy).
+void ilu_solve(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const int32_t* urows,
+               const int64_t* uptr, const int64_t* lo, const int64_t* dg, const int64_t* hi, const int32_t* col,
+               const double* fv, double* y, int64_t ldy, int R, hipStream_t s);
+
 // ---------------------------------------------------------------- Krylov state
 constexpr int kMaxRhs = 8;
 constexpr int kVecGrid = 1024;  // workgroups of the grid-stride vector kernels

@@ -131,7 +131,7 @@ __global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ p
   const int64_t lr = B.pad + (r - B.s);
   const int64_t kr = lr / t, rr = lr % t;
   T* __restrict__ G = spikes + B.goff;
-  T* __restrict__ W = tiles + B.tiles;
+  T* __restrict__ W = tiles ? tiles + B.tiles : nullptr;   // null: no tiles (incomplete factors)
   for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
     const int64_t c = col[q];
     const double v = val[q];
@@ -143,7 +143,7 @@ __global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ p
       else if (kc == kr + 1 && rr >= cc) idx = B.T * tt + kr * pt + cc * t + rr;      // A_{k,k+1}
       else if (kc == kr - 1 && rr <= cc) idx = B.T * tt + kc * pt + t + cc * t + rr;  // A_{k+1,k}
       else { atomicOr(flags, 8u); continue; }
-      W[idx] += (T)v;
+      if (W) W[idx] += (T)v;
     } else if (c < B.s) {
       const int64_t jj = c - (B.s - t);
       const int64_t ir = r - B.s;
@@ -254,11 +254,11 @@ void setup_scatter(int dtype, int64_t n, int p, int t, const int64_t* part, cons
   if (dtype == 0) {
     hipLaunchKernelGGL(k_scatter<double>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
                        row_ptr, col, val, (double*)tiles, (double*)spikes, (double*)rhs, colnorm, flags);
-    hipLaunchKernelGGL(k_pad_identity<double>, dim3(p), dim3(256), 0, s, p, t, blocks, (double*)tiles);
+    if (tiles) hipLaunchKernelGGL(k_pad_identity<double>, dim3(p), dim3(256), 0, s, p, t, blocks, (double*)tiles);
   } else {
     hipLaunchKernelGGL(k_scatter<float>, dim3((unsigned)nb), dim3(256), 0, s, n, p, t, part, blocks,
                        row_ptr, col, val, (float*)tiles, (float*)spikes, (float*)rhs, colnorm, flags);
-    hipLaunchKernelGGL(k_pad_identity<float>, dim3(p), dim3(256), 0, s, p, t, blocks, (float*)tiles);
+    if (tiles) hipLaunchKernelGGL(k_pad_identity<float>, dim3(p), dim3(256), 0, s, p, t, blocks, (float*)tiles);
   }
 }
 

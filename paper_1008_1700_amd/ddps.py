@@ -51,6 +51,7 @@ class ddps_options(ctypes.Structure):
         ("reduced_solve", ctypes.c_int32),
         ("loosen_ratio", ctypes.c_double),
         ("gemv_sums", ctypes.c_int32),
+        ("block_factor", ctypes.c_int32),
     ]
 
 
@@ -507,7 +508,7 @@ class Solver:
     def __init__(self, A, part_ptr, dtype="f64", delta=0.0, inner_tol=1e-12, inner_maxit=1000,
                  outer_maxit=1000, outer="refine", max_rhs=1, guess=False, device="cuda", stream=None,
                  mem_budget=0, streams=0, graph=False, inner_prec=0, retrieval=0, norm=0, work_slots=0,
-                 reduced="bicgstab", loosen_ratio=0.0, gemv_sums=0):
+                 reduced="bicgstab", loosen_ratio=0.0, gemv_sums=0, block_factor="lu"):
         import torch
         self.n = A.n
         self.p = len(part_ptr) - 1
@@ -530,6 +531,7 @@ class Solver:
         o.reduced_solve = 1 if reduced == "direct" else 0
         o.loosen_ratio = float(loosen_ratio)
         o.gemv_sums = int(gemv_sums)
+        o.block_factor = {"lu": 0, "ilu0": 1}[block_factor]
         st = stream if stream is not None else torch.cuda.current_stream(device)
         o.stream = ctypes.c_void_p(st.cuda_stream)
         self.opt = o

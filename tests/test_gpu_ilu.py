@@ -1,0 +1,185 @@
+"""GPU parity of the incomplete block factors (block_factor = 1, ILU(0) of
+every A_ii, Section 3's L~_i U~_i): the block solve, the reduced matrix
+built from the incomplete spikes' tips, one preconditioner application and
+whole solves, against the oracle's ILU(0) form on the same inputs.
+
+Tolerances: the ILU factors are FP64 and unique (no pivoting), so the block
+solve and the FP64 tips match the oracle to 1e-12 relative; solves to the
+1e-8 relative-error bar at a residual tolerance of 1e-10 (the outer layer
+wins back what the incomplete factors leave).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from tests.gpu_util import dev_vec, host, make_solver, relerr, torch_cuda
+from workloads import configs, pde
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(d, delta=0.0):
+    from oracle import ddps_oracle as O
+    A = d["A"]
+    return O.Preconditioner(A.n, A.row_ptr, A.col, A.val, d["part_ptr"], delta, block_factor="ilu0")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return configs.c1()
+
+
+@pytest.fixture(scope="module")
+def c1_ilu(c1):
+    print("ILU(0) C1 f64 setup", flush=True)
+    S = make_solver(c1, inner_tol=1e-14, max_rhs=2, retrieval=1, block_factor="ilu0", outer="bicgstab")
+    S.factor()
+    yield S
+    S.close()
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    return _oracle(c1)
+
+
+def test_ilu_block_solve(c1, c1_ilu, c1_oracle):
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    y = np.random.default_rng(21).standard_normal((2, c1["A"].n))
+    g = torch.empty(2 * c1["A"].n, dtype=torch.float64, device="cuda")
+    ddps.ddps_block_solve(c1_ilu.h, 2, dev_vec(y.ravel()), g)
+    got = host(g).reshape(2, -1)
+    for j in range(2):
+        exp = np.concatenate([O.solve_with(f, y[j, b.lo:b.hi]) for f, b in zip(c1_oracle.factors, c1_oracle.blocks)])
+        assert relerr(got[j], exp) <= 1e-12
+
+
+def test_ilu_reduced_matvec(c1_ilu, c1_oracle):
+    """G^ from the tips of the incomplete spikes (every coupling column of
+    C1 is kept, so the reduced layout is the oracle's c)."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    m, t, _ = ddps.ddps_reduced_layout(c1_ilu.h)
+    assert m == c1_oracle.m == 384
+    x = np.random.default_rng(22).standard_normal(m)
+    v = torch.empty(m, dtype=torch.float64, device="cuda")
+    ddps.ddps_reduced_matvec(c1_ilu.h, 1, dev_vec(x), v)
+    assert relerr(host(v), c1_oracle.ghat_matvec(x)) <= 1e-12
+
+
+def test_ilu_preconditioner_application(c1, c1_ilu, c1_oracle):
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    y = np.random.default_rng(23).standard_normal(c1["A"].n)
+    z = torch.empty(c1["A"].n, dtype=torch.float64, device="cuda")
+    gh = torch.empty(384, dtype=torch.float64, device="cuda")
+    zh = torch.empty(384, dtype=torch.float64, device="cuda")
+    ddps.ddps_apply_preconditioner(c1_ilu.h, 1, dev_vec(y), z, gh, zh)
+    ze, d = c1_oracle.apply(y, reduced="dense", retrieval="resolve")
+    assert relerr(host(gh), d["ghat"]) <= 1e-12
+    assert relerr(host(zh), d["zhat"]) <= 1e-10
+    assert relerr(host(z), ze) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype,reduced", [("f64", "bicgstab"), ("f32", "bicgstab"), ("bf16x3", "bicgstab"),
+                                           ("f64", "direct")])
+def test_ilu_solve(c1, dtype, reduced):
+    """Whole solves with the outer BiCGStab: the direct solution to 1e-8, and
+    the oracle's ILU(0) DDPS; the GPU needs more outer iterations than with
+    exact factors, as the oracle does."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    A = c1["A"]
+    print(f"ILU(0) C1 solve {dtype} {reduced}", flush=True)
+    S = make_solver(c1, dtype=dtype, inner_tol=1e-10, retrieval=1, block_factor="ilu0", outer="bicgstab",
+                    reduced=reduced)
+    try:
+        S.factor()
+        f = c1["f"]
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, info = S.solve(dev_vec(f), x, 1e-10, check=False)
+        xo, oinfo, _ = O.solve(A.n, A.row_ptr, A.col, A.val, c1["part_ptr"], f, tol=1e-10, outer="bicgstab",
+                               block_factor="ilu0", reduced="dense")
+        print(f"  GPU {info.as_dict()}; oracle outer {oinfo.outer_iters}", flush=True)
+        assert rc == 0 and info.relres_inf <= 1e-10
+        xd = O.direct_solve(A.scipy(), f)
+        assert relerr(host(x), xd) <= 1e-8
+        assert relerr(host(x), xo) <= 1e-8
+        assert info.outer_iters >= 1.0
+    finally:
+        S.close()
+
+
+def test_ilu_general_sparse():
+    """A general sparse matrix made banded by reverse Cuthill-McKee, with
+    dropped coupling (delta 0.4) and incomplete factors."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    A = pde.random_geometric(6000, 8, 5)
+    gs = ddps.GeneralSystem(A.n, A.row_ptr, A.col, A.val, 8)
+    xs = np.random.default_rng(6).uniform(-1, 1, A.n)
+    f = A.scipy() @ xs
+    print(f"ILU(0) general sparse p {len(gs.part_ptr) - 1} b {gs.b}", flush=True)
+    S = ddps.Solver(gs, gs.part_ptr, dtype="f64", delta=0.4, outer="bicgstab", inner_tol=1e-10, retrieval=1,
+                    block_factor="ilu0")
+    try:
+        S.factor()
+        xp = torch.zeros(gs.n, dtype=torch.float64, device="cuda")
+        rc, info = S.solve(dev_vec(gs.to_perm(f)), xp, 1e-10, check=False)
+        print(f"  GPU {info.as_dict()}", flush=True)
+        assert rc == 0 and info.relres_inf <= 1e-10
+        xg = gs.from_perm(host(xp))
+        assert relerr(xg, O.direct_solve(A.scipy(), f)) <= 1e-8
+    finally:
+        S.close()
+
+
+def test_ilu_zero_pivot_is_reported(c1):
+    """A zero pivot of the incomplete factors (the first row of block 2 with
+    its diagonal set to 0: u_rr = a_rr there) is DDPS_E_SINGULAR with that
+    block and row."""
+    from paper_1008_1700_amd import ddps
+    A = c1["A"]
+    r = int(c1["part_ptr"][2])
+    val = A.val.copy()
+    q = [k for k in range(A.row_ptr[r], A.row_ptr[r + 1]) if A.col[k] == r][0]
+    val[q] = 0.0
+    B = pde.CSR(A.n, A.row_ptr, A.col, val)
+    S = ddps.Solver(B, c1["part_ptr"], retrieval=1, block_factor="ilu0")
+    try:
+        with pytest.raises(ddps.DDPSError) as e:
+            S.factor()
+        assert e.value.code == -4   # DDPS_E_SINGULAR
+        blk, row = ddps.ddps_last_singular(S.h)
+        assert (blk, row) == (2, r)
+    finally:
+        S.close()
+
+
+def test_ilu_option_errors(c1):
+    """Incomplete factors keep only the tips (retrieval 0 is refused), need a
+    stored diagonal in every row, and keep no tiles."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    with pytest.raises(ddps.DDPSError):
+        make_solver(c1, retrieval=0, block_factor="ilu0")
+    A = c1["A"]
+    S = A.scipy().copy()   # scipy() shares A's arrays
+    S.setdiag(0.0)
+    S.eliminate_zeros()
+    S.sort_indices()
+    B = pde.CSR(A.n, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.astype(np.float64))
+    with pytest.raises(ddps.DDPSError):
+        ddps.Solver(B, c1["part_ptr"], retrieval=1, block_factor="ilu0")
+    G = make_solver(c1, retrieval=1, block_factor="ilu0")
+    try:
+        G.factor()
+        buf = torch.empty(64 * 64, dtype=torch.float64, device="cuda")
+        with pytest.raises(ddps.DDPSError):
+            ddps.ddps_get_tile(G.h, 0, 0, 0, buf)
+    finally:
+        G.close()

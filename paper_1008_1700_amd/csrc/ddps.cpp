@@ -124,6 +124,7 @@ struct ddps_ctx {
   double* d_fv = nullptr;
   int64_t *d_ilo = nullptr, *d_idg = nullptr, *d_ihi = nullptr, *d_lptr = nullptr, *d_uptr = nullptr;
   int32_t *d_lrows = nullptr, *d_urows = nullptr, *d_ibatch = nullptr;
+  int64_t *d_lq = nullptr, *d_uq = nullptr;   // entry ranges per level-ordered row (pairs)
   IluBlock* d_iblk = nullptr;
   void* d_iws = nullptr;
   int64_t ilu_nmax = 0, ilu_nnz = 0, ilu_levels = 0;
@@ -1328,8 +1329,8 @@ int block_solves(ddps_ctx* h, int tk) {
   }
   hipEvent_t a;
   h->tim_begin(tk, a);
-  ilu_solve(h->p, h->d_iblk, h->d_lrows, h->d_lptr, h->d_urows, h->d_uptr, h->d_ilo, h->d_idg, h->d_ihi, h->d_col,
-            h->d_fv, h->d_ypad, h->Np, R, h->stream);
+  ilu_solve(h->p, h->d_iblk, h->d_lrows, h->d_lptr, h->d_lq, h->d_urows, h->d_uptr, h->d_uq, h->d_col, h->d_fv,
+            h->d_ypad, h->Np, R, h->d_vpad, h->stream);
   // both triangles once (values and column indices), each vector entry read and written per sweep
   h->tim_end(tk, a, 2.0 * (double)h->ilu_nnz * R, 12.0 * (double)h->ilu_nnz + 32.0 * (double)h->n * R);
   HIPCHK(hipGetLastError());
@@ -1793,7 +1794,7 @@ int ilu_plan(ddps_ctx* h, IluPlan& P) {
 }
 
 size_t ilu_plan_bytes(const ddps_ctx* h, const IluPlan& P) {
-  return (size_t)h->nnz * 8 + (size_t)h->n * (3 * 8 + 2 * 4) + (P.lptr.size() + P.uptr.size()) * 8 +
+  return (size_t)h->nnz * 8 + (size_t)h->n * (3 * 8 + 2 * 4 + 2 * 16) + (P.lptr.size() + P.uptr.size()) * 8 +
          (size_t)h->p * (sizeof(IluBlock) + 4);
 }
 
@@ -1803,8 +1804,22 @@ int ilu_upload(ddps_ctx* h, const IluPlan& P) {
   if ((rc = h->alloc(h->d_fv, h->nnz)) || (rc = h->alloc(h->d_ilo, n)) || (rc = h->alloc(h->d_idg, n)) ||
       (rc = h->alloc(h->d_ihi, n)) || (rc = h->alloc(h->d_lrows, n)) || (rc = h->alloc(h->d_urows, n)) ||
       (rc = h->alloc(h->d_lptr, (int64_t)P.lptr.size())) || (rc = h->alloc(h->d_uptr, (int64_t)P.uptr.size())) ||
-      (rc = h->alloc(h->d_iblk, p)) || (rc = h->alloc(h->d_ibatch, p)))
+      (rc = h->alloc(h->d_iblk, p)) || (rc = h->alloc(h->d_ibatch, p)) || (rc = h->alloc(h->d_lq, 2 * n)) ||
+      (rc = h->alloc(h->d_uq, 2 * n)))
     return rc;
+  {
+    std::vector<int64_t> q(2 * n);
+    for (int64_t j = 0; j < n; ++j) {
+      q[2 * j] = P.lo[P.lrows[j]];
+      q[2 * j + 1] = P.dg[P.lrows[j]];
+    }
+    HIPCHK(hipMemcpy(h->d_lq, q.data(), sizeof(int64_t) * 2 * n, hipMemcpyHostToDevice));
+    for (int64_t j = 0; j < n; ++j) {
+      q[2 * j] = P.dg[P.urows[j]] + 1;
+      q[2 * j + 1] = P.hi[P.urows[j]];
+    }
+    HIPCHK(hipMemcpy(h->d_uq, q.data(), sizeof(int64_t) * 2 * n, hipMemcpyHostToDevice));
+  }
   std::vector<int32_t> order(p);
   for (int i = 0; i < p; ++i) order[i] = i;
   hipStream_t s = h->stream;

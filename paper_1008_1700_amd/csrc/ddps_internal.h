@@ -132,9 +132,12 @@ void ilu_spikes(int dtype, int nb, const IluBlock* blocks, const int32_t* batch,
                 const int64_t* lo, const int64_t* dg, const int64_t* hi, const int32_t* col, const double* fv,
                 void* ws, int64_t slot_elems, void* tips, hipStream_t s);
 // y = D~^{-1} y in place on the padded vector (R columns, stride ldy).
-void ilu_solve(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const int32_t* urows,
-               const int64_t* uptr, const int64_t* lo, const int64_t* dg, const int64_t* hi, const int32_t* col,
-               const double* fv, double* y, int64_t ldy, int R, hipStream_t s);
+// lq / uq: int64 pairs per level-ordered slot of lrows / urows, the entry
+// range of that row's L~ part [lo, dg) / of its U~ part [dg + 1, hi).
+// yt: work vector of the same size as y (ldy * R doubles, ldy >= padded rows).
+void ilu_solve(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const void* lq,
+               const int32_t* urows, const int64_t* uptr, const void* uq, const int32_t* col, const double* fv,
+               double* y, int64_t ldy, int R, double* yt, hipStream_t s);
 
 // ---------------------------------------------------------------- Krylov state
 constexpr int kMaxRhs = 8;

@@ -162,43 +162,84 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_tips(const IluBlock* __rest
 }
 
 // D~^{-1} y for every block, in place on the padded vector (R columns,
-// column stride ldy), one workgroup per block: forward solve with L~ level
-// by level, then backward with U~.
-__global__ __launch_bounds__(kIluThreads) void k_ilu_solve(const IluBlock* __restrict__ blocks,
-                                                             const int32_t* __restrict__ lrows,
-                                                             const int64_t* __restrict__ lptr,
-                                                             const int32_t* __restrict__ urows,
-                                                             const int64_t* __restrict__ uptr,
-                                                             const int64_t* __restrict__ lo,
-                                                             const int64_t* __restrict__ dg,
-                                                             const int64_t* __restrict__ hi,
-                                                             const int32_t* __restrict__ col,
-                                                             const double* __restrict__ fv, double* y, int64_t ldy,
-                                                             int R) {
+// column stride ldy), one workgroup of kSolveThreads per block: forward
+// solve with L~ level by level, then backward with U~.  The solve is bound
+// by the latency of its dependent loads (level list -> row -> entries ->
+// vector), so each level-ordered slot carries its row's entry range (lq:
+// [lo, dg) of the forward order, uq: [dg + 1, hi) of the backward one,
+// pivot at uq.x - 1), read together with the row number, and a workgroup
+// runs 16 waves; the R lanes of one row are adjacent.  Entries are taken
+// four at a time with their loads issued together (columns and values,
+// then the vector entries), so a row costs three dependent loads, not two
+// per entry.
+constexpr int kSolveThreads = 1024;
+
+// acc - sum over q in [q0, q1) of fv[q] * Yc[(col[q] - s) * R]
+__device__ __forceinline__ double row_dot(double acc, int64_t q0, int64_t q1, const int32_t* __restrict__ col,
+                                          const double* __restrict__ fv, const double* Yc, int64_t s, int R) {
+  for (int64_t q = q0; q < q1; q += 4) {
+    int64_t c[4];
+    double v[4], x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = q + u < q1;
+      c[u] = ok ? ((int64_t)col[q + u] - s) * R : 0;
+      v[u] = ok ? fv[q + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = q + u < q1 ? Yc[c[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc -= v[u] * x[u];
+  }
+  return acc;
+}
+__global__ __launch_bounds__(kSolveThreads) void k_ilu_solve(const IluBlock* __restrict__ blocks,
+                                                               const int32_t* __restrict__ lrows,
+                                                               const int64_t* __restrict__ lptr,
+                                                               const longlong2* __restrict__ lq,
+                                                               const int32_t* __restrict__ urows,
+                                                               const int64_t* __restrict__ uptr,
+                                                               const longlong2* __restrict__ uq,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ fv, double* y,
+                                                               int64_t ldy, int R, double* __restrict__ yt) {
   const IluBlock B = blocks[blockIdx.x];
-  // entry of global row r in column j: y[j * ldy + vbase + (r - s)]
+  // y: entry of global row r in column j at y[j * ldy + vbase + (r - s)].
+  // The solves run on a row-major copy (yt + vbase * R, R entries per row),
+  // so that the R lanes of a row read one stretch of R doubles.
+  double* __restrict__ Yt = yt + B.vbase * R;
+  const int64_t nR = B.n * R;
+  for (int64_t w = threadIdx.x; w < nR; w += blockDim.x) {
+    const int64_t r = w % B.n, j = w / B.n;
+    Yt[r * R + j] = y[j * ldy + B.vbase + r];
+  }
+  __syncthreads();
   for (int64_t lv = 0; lv < B.lnum; ++lv) {
     const int64_t a = lptr[B.lbeg + lv], e = lptr[B.lbeg + lv + 1];
     for (int64_t w = threadIdx.x; w < (e - a) * R; w += blockDim.x) {
-      const int64_t r = lrows[a + w / R];
-      double* __restrict__ Yc = y + (w % R) * ldy + B.vbase;
-      double acc = Yc[r - B.s];
-      for (int64_t q = lo[r]; q < dg[r]; ++q) acc -= fv[q] * Yc[col[q] - B.s];
-      Yc[r - B.s] = acc;
+      const int64_t j = a + w / R;
+      const int64_t r = lrows[j];
+      const longlong2 qr = lq[j];
+      double* __restrict__ Yc = Yt + (w % R);
+      Yc[(r - B.s) * R] = row_dot(Yc[(r - B.s) * R], qr.x, qr.y, col, fv, Yc, B.s, R);
     }
     __syncthreads();
   }
   for (int64_t lv = 0; lv < B.unum; ++lv) {
     const int64_t a = uptr[B.ubeg + lv], e = uptr[B.ubeg + lv + 1];
     for (int64_t w = threadIdx.x; w < (e - a) * R; w += blockDim.x) {
-      const int64_t r = urows[a + w / R];
-      double* __restrict__ Yc = y + (w % R) * ldy + B.vbase;
-      const int64_t d = dg[r];
-      double acc = Yc[r - B.s];
-      for (int64_t q = d + 1; q < hi[r]; ++q) acc -= fv[q] * Yc[col[q] - B.s];
-      Yc[r - B.s] = acc / fv[d];
+      const int64_t j = a + w / R;
+      const int64_t r = urows[j];
+      const longlong2 qr = uq[j];
+      double* __restrict__ Yc = Yt + (w % R);
+      const double piv = fv[qr.x - 1];
+      Yc[(r - B.s) * R] = row_dot(Yc[(r - B.s) * R], qr.x, qr.y, col, fv, Yc, B.s, R) / piv;
     }
     __syncthreads();
+  }
+  for (int64_t w = threadIdx.x; w < nR; w += blockDim.x) {
+    const int64_t r = w % B.n, j = w / B.n;
+    y[j * ldy + B.vbase + r] = Yt[r * R + j];
   }
 }
 
@@ -230,11 +271,11 @@ void ilu_spikes(int dtype, int nb, const IluBlock* blocks, const int32_t* batch,
   }
 }
 
-void ilu_solve(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const int32_t* urows,
-               const int64_t* uptr, const int64_t* lo, const int64_t* dg, const int64_t* hi, const int32_t* col,
-               const double* fv, double* y, int64_t ldy, int R, hipStream_t s) {
-  hipLaunchKernelGGL(k_ilu_solve, dim3(p), dim3(kIluThreads), 0, s, blocks, lrows, lptr, urows, uptr, lo, dg, hi, col,
-                     fv, y, ldy, R);
+void ilu_solve(int p, const IluBlock* blocks, const int32_t* lrows, const int64_t* lptr, const void* lq,
+               const int32_t* urows, const int64_t* uptr, const void* uq, const int32_t* col, const double* fv,
+               double* y, int64_t ldy, int R, double* yt, hipStream_t s) {
+  hipLaunchKernelGGL(k_ilu_solve, dim3(p), dim3(kSolveThreads), 0, s, blocks, lrows, lptr, (const longlong2*)lq, urows,
+                     uptr, (const longlong2*)uq, col, fv, y, ldy, R, yt);
 }
 
 }  // namespace ddps

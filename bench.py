@@ -19,10 +19,12 @@ of 32 random right-hand sides of the same matrix.  The same solver without
 the learned guess, the plain FP64 solver (the paper's method: unpreconditioned
 inner BiCGStab; spike tips only and re-solved retrieval, which is what fits in
 memory), and FP64 with the same inner preconditioner are timed on the same GPU
-in the same run.
+in the same run.  So is the path with incomplete block factors (ILU(0) of
+every block, FP32 tips, the outer BiCGStab), reported under "ilu0".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode M] [--config c5|c2|c3|c1] [--no-cpu]
        python bench.py --config c4 [--mode M]   (learned-guess time sequence)
+       python bench.py --ilu-only               (only the incomplete-factor leg)
 """
 from __future__ import annotations
 
@@ -206,6 +208,70 @@ def run_mode(d, mode, steps, warmup, tol, inner_tol, timing_kind="gemm", graph_s
     if kappa:
         out["kappa_inf"] = kappa_inf_certificate(S, d)
         log(f"{mode}: kappa_inf {out['kappa_inf']}")
+    S.close()
+    del f, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_ilu(d, mode, steps, warmup, tol, inner_tol, inner_prec=1):
+    """The same whole path with incomplete block factors (ILU(0) of every
+    A_ii, Section 3's L~_i U~_i; tips only, re-solved retrieval) and the
+    outer BiCGStab that wins back what they leave: `steps` timed steps
+    (refresh values, factor, solve) after `warmup`, then one untimed step
+    with the ILU block solves timed by HIP events."""
+    import torch
+    from paper_1008_1700_amd import ddps
+    A = d["A"]
+    fh = d["f"]
+    k = 1 if fh.ndim == 1 else fh.shape[1]
+    S = ddps.Solver(A, d["part_ptr"], dtype=mode, inner_tol=inner_tol, outer="bicgstab", max_rhs=k,
+                    inner_prec=inner_prec, retrieval=1, block_factor="ilu0")
+    f = torch.from_numpy(np.ascontiguousarray(fh.T if k > 1 else fh)).cuda()
+    x = torch.zeros((k, A.n) if k > 1 else (A.n,), dtype=torch.float64, device="cuda")
+    log(f"ilu0 {mode}: setup done, {ddps.ddps_memory(S.h) / 1e9:.1f} GB")
+
+    def step():
+        x.zero_()
+        ddps.ddps_refactor_values(S.h, S.val)
+        ddps.ddps_factor(S.h)
+        return ddps.ddps_solve_many(S.h, f.reshape(k, A.n), x.reshape(k, A.n), tol, check=False)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, info = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"ilu0 {mode}: {ms:.1f} ms per step (factor {info.t_factor_ms:.1f}, solve {info.t_solve_ms:.1f}, "
+        f"{info.outer_iters} outer its, {info.applications} applications)")
+    xs = x.reshape(k, A.n).cpu().numpy().T
+    sweeps = dict(launches=0, ms=0.0, bytes=0.0)
+    for kind in ("sweep", "retrieval"):
+        ddps.ddps_timing_read(S.h, kind)
+        ddps.ddps_timing_enable(S.h, kind, True)
+    step()
+    torch.cuda.synchronize()
+    for kind in ("sweep", "retrieval"):
+        ddps.ddps_timing_enable(S.h, kind, False)
+        tk = ddps.ddps_timing_read(S.h, kind)
+        for q in ("launches", "ms", "bytes"):
+            sweeps[q] += tk[q]
+    r = fh.reshape(A.n, k) - A.scipy() @ xs
+    nf = np.linalg.norm(fh.reshape(A.n, k), np.inf, axis=0)
+    xst = d["x_star"].reshape(A.n, k)
+    out = dict(mode=mode, block_factor="ilu0", rc=rc, ms_per_step=ms, steps=steps, factor_ms=info.t_factor_ms,
+               solve_ms=info.t_solve_ms, outer_iters=info.outer_iters, applications=info.applications,
+               inner_iters_avg=info.inner_iters_avg, inner_tol=inner_tol, inner_prec=inner_prec,
+               relres_inf=float(np.max(np.max(np.abs(r), axis=0) / nf)),
+               relerr_xstar=float(np.max(np.linalg.norm(xs - xst, axis=0) / np.linalg.norm(xst, axis=0))),
+               block_solve=dict(kernel="k_ilu_solve", launches=sweeps["launches"],
+                                avg_launch_us=sweeps["ms"] * 1e3 / max(sweeps["launches"], 1),
+                                algorithmic_bytes_per_launch=sweeps["bytes"] / max(sweeps["launches"], 1),
+                                GBps=sweeps["bytes"] / (sweeps["ms"] * 1e-3) / 1e9 if sweeps["ms"] > 0 else None),
+               mem_gb=ddps.ddps_memory(S.h) / 1e9)
     S.close()
     del f, x
     torch.cuda.empty_cache()
@@ -515,6 +581,7 @@ TUNE_CACHE = os.path.join(ROOT, "paper_1008_1700_amd", "tune_cache.json")
 # workload (C5: mixed 1e-4 1646 ms vs 1e-5 1715 ms vs 1e-6 1842 ms; FP64
 # 1e-5 4272 ms, 1e-6..1e-9 4309-4314 ms; C2: mixed 1e-6, FP64 1e-9)
 INNER_TOL = {"c5": (1e-4, 1e-5), "c2": (1e-6, 1e-9), "c3": (1e-6, 1e-9), "c1": (1e-6, 1e-9)}
+ILU_INNER_TOL = 1e-4   # reduced-solve tolerance of the incomplete-factor leg
 
 
 def main():
@@ -556,6 +623,9 @@ def main():
     ap.add_argument("--c4-steps", type=int, default=300)
     ap.add_argument("--c4-train", type=int, default=200)
     ap.add_argument("--c4-epochs", type=int, default=200)
+    ap.add_argument("--no-ilu", action="store_true", help="skip the incomplete-factor (ILU(0)) run")
+    ap.add_argument("--ilu-only", action="store_true", help="only run the incomplete-factor leg (one JSON line)")
+    ap.add_argument("--ilu-steps", type=int, default=1)
     args = ap.parse_args()
     it_mix, it_f64 = INNER_TOL.get(args.config, INNER_TOL["c2"])
     args.inner_tol = it_mix if args.inner_tol is None else args.inner_tol
@@ -576,6 +646,13 @@ def main():
     log(f"building workload {args.config}")
     d = build_workload(args.config)
     log(f"n={d['A'].n} nnz={d['A'].nnz} p={len(d['part_ptr']) - 1}")
+    ilu_mode = "f64" if args.mode == "f64" else "f32"
+    if args.ilu_only:
+        ilu = run_ilu(d, ilu_mode, args.ilu_steps, 1, args.tol, ILU_INNER_TOL, args.inner_prec)
+        print(json.dumps(dict(metric="DDPS time-to-solution @rel.resid 1e-10, ILU(0) block factors", value=ilu["ms_per_step"],
+                              unit="ms", higher_is_better=False, n_gpus=1, dtype=ilu_mode,
+                              config={"workload": WORKLOADS.get(args.config, args.config)}, ilu0=ilu)), flush=True)
+        return
     itol = args.inner_tol_f64 if args.mode == "f64" else args.inner_tol
     iprec = args.inner_prec
     learned = None if (args.no_learned or args.mode == "f64" or args.reduced == "direct" or
@@ -639,6 +716,11 @@ def main():
         roof_gemv = dict(bound="hbm", achieved=bw / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s", frac=bw / HBM_PEAK,
                          kernel="k_gemv (reduced products, block sweeps, retrieval)", launches=g["launches"],
                          algorithmic_bytes=g["bytes"], ms=g["ms"], per_kind=g["per_kind"])
+    ilu = None
+    if not args.no_ilu and len(d["part_ptr"]) > 2:
+        ilu = run_ilu(d, ilu_mode, args.ilu_steps, 1, args.tol, ILU_INNER_TOL, iprec)
+        ilu["vs_exact_factors"] = ilu["ms_per_step"] / res["ms_per_step"]
+        log(f"ilu0: {json.dumps(ilu)}")
     cpu = None if args.no_cpu else cpu_baseline(d)
     speed = (base["ms_per_step"] / res["ms_per_step"]) if base and base.get("ms_per_step") else None
     speed_same = (base_same["ms_per_step"] / res["ms_per_step"]) if base_same else None
@@ -676,6 +758,7 @@ def main():
         "algorithmic_flops_factor": alg,
         "roofline": roof,
         "roofline_gemv": roof_gemv,
+        "ilu0": ilu,
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
     }

@@ -183,3 +183,29 @@ def test_ilu_option_errors(c1):
             ddps.ddps_get_tile(G.h, 0, 0, 0, buf)
     finally:
         G.close()
+
+
+def test_ilu_single_block():
+    """p = 1: no coupling, no reduced system; the preconditioner is D~ =
+    L~ U~ of the whole matrix and the outer BiCGStab does the rest."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    cfg = configs.small_banded(1, [700], 9, 5)
+    A = cfg["A"]
+    print("ILU(0) p = 1", flush=True)
+    S = ddps.Solver(A, cfg["part_ptr"], retrieval=1, block_factor="ilu0", outer="bicgstab")
+    try:
+        S.factor()
+        y = np.random.default_rng(24).standard_normal(A.n)
+        z = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        ddps.ddps_apply_preconditioner(S.h, 1, dev_vec(y), z)
+        fac = O.factor_block_ilu0(A.scipy())
+        assert relerr(host(z), O.ilu0_solve(fac, y)) <= 1e-12
+        f = cfg["f"]
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, info = S.solve(dev_vec(f), x, 1e-10, check=False)
+        assert rc == 0 and info.relres_inf <= 1e-10
+        assert relerr(host(x), O.direct_solve(A.scipy(), f)) <= 1e-8
+    finally:
+        S.close()

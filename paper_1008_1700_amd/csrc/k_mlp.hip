@@ -14,61 +14,145 @@ namespace ddps {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Tile 64 x 64, 256 threads = 4 waves (2 x 2), each one 32 x 32 MFMA block.
+// Tile T x T (T = 64 or 128), 256 threads = 4 waves (2 x 2), each a
+// (T/2) x (T/2) sub-tile of 32 x 32 MFMA blocks; K advances in chunks of 32
+// through LDS in layout [row][k] (k contiguous, padded by 8), and the next
+// chunk's global loads are held in registers while the current one is
+// multiplied.  Every operand is read in segments of 8 elements along its
+// contiguous dimension: one 16-byte load when the leading dimension and the
+// base allow it and the segment is inside the matrix, four 4-byte loads when
+// only 4-byte alignment holds, else one element at a time with zero fill.
+// Per output element the products are summed in the same K order whatever
+// T is (chunks of 32, two 16-deep MFMAs each).
 // MFMA operand X = A block (32 m x 16 k): lane l holds A[l%32][8(l/32)..+8);
 // operand Y = B block (16 k x 32 n): lane l holds B[8(l/32)..+8)[l%32];
 // register v of lane l is C[8(v/4) + 4(l/32) + v%4][l%32].
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_mlp_gemm(int M, int N, int K, const __bf16* __restrict__ A, int lda,
-                                                  const __bf16* __restrict__ B, int ldb,
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// 8 elements p[0..8) (contiguous), the first `valid` of them in range;
+// vw: 8 = 16-byte loads allowed, 2 = 4-byte loads allowed, 1 = elements.
+__device__ __forceinline__ u16x8 load_seg(const unsigned short* __restrict__ p, int valid, int vw) {
+  u16x8 r;
+  if (valid >= 8 && vw == 8) return *(const u16x8*)p;
+  if (valid >= 8 && vw == 2) {
+    const unsigned int* q = (const unsigned int*)p;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned int w = q[e];
+      r[2 * e] = (unsigned short)(w & 0xffffu);
+      r[2 * e + 1] = (unsigned short)(w >> 16);
+    }
+    return r;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = e < valid ? p[e] : (unsigned short)0;
+  return r;
+}
+
+template <bool TA, bool TB, int T>
+__global__ __launch_bounds__(256) void k_mlp_gemm(int M, int N, int K, const __bf16* __restrict__ A_, int lda,
+                                                  const __bf16* __restrict__ B_, int ldb,
                                                   const float* __restrict__ bias, int epi,
-                                                  float* __restrict__ Cf, __bf16* __restrict__ Cb, int ldc) {
+                                                  float* __restrict__ Cf, __bf16* __restrict__ Cb, int ldc,
+                                                  int va, int vb) {
   constexpr int BK = 32, LDK = BK + 8;
-  __shared__ __attribute__((aligned(16))) __bf16 As[64][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[64][LDK];
-  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  constexpr int SEG = T * BK / 8 / 256;   // segments per thread and operand
+  constexpr int WB = T / 64;              // 32 x 32 blocks per wave and dimension
+  __shared__ __attribute__((aligned(16))) unsigned short As[T][LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[T][LDK];
+  const unsigned short* A = (const unsigned short*)A_;
+  const unsigned short* B = (const unsigned short*)B_;
+  const int m0 = blockIdx.x * T, n0 = blockIdx.y * T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  f32x16 acc;
+  f32x16 acc[WB][WB];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  // staging: thread -> (row = tid / 4, k = 8 (tid % 4) .. +8)
-  const int sr = tid >> 2, sk = 8 * (tid & 3);
-  const __bf16 zero = (__bf16)0.f;
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int i = 0; i < WB; ++i)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int m = m0 + sr, k = k0 + sk + e;
-      __bf16 av = zero;
-      if (m < M && k < K) av = TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k];
-      As[sr][sk + e] = av;
-      const int n = n0 + sr;
-      __bf16 bv = zero;
-      if (n < N && k < K) bv = TB ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n];
-      Bs[sr][sk + e] = bv;
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  // Segment q of a chunk: with the operand's k contiguous (A, or B stored
+  // transposed) it is (row q / 4, k 8 (q % 4)); with rows contiguous (A
+  // stored transposed, or B) it is (k q / (T/8), row 8 (q % (T/8))).
+  u16x8 ra[SEG], rb[SEG];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int q = tid + 256 * j;
+      if (!TA) {
+        const int r = q >> 2, k = k0 + 8 * (q & 3), m = m0 + r;
+        ra[j] = load_seg(A + (int64_t)m * lda + k, m < M ? K - k : 0, va);
+      } else {
+        const int k = k0 + q / (T / 8), r = 8 * (q % (T / 8)), m = m0 + r;
+        ra[j] = load_seg(A + (int64_t)k * lda + m, k < K ? M - m : 0, va);
+      }
+      if (TB) {
+        const int r = q >> 2, k = k0 + 8 * (q & 3), n = n0 + r;
+        rb[j] = load_seg(B + (int64_t)n * ldb + k, n < N ? K - k : 0, vb);
+      } else {
+        const int k = k0 + q / (T / 8), r = 8 * (q % (T / 8)), n = n0 + r;
+        rb[j] = load_seg(B + (int64_t)k * ldb + n, k < K ? N - n : 0, vb);
+      }
     }
+  };
+  auto stage = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int q = tid + 256 * j;
+      if (!TA) {
+        *(u16x8*)&As[q >> 2][8 * (q & 3)] = ra[j];
+      } else {
+        const int k = q / (T / 8), r = 8 * (q % (T / 8));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[r + e][k] = ra[j][e];
+      }
+      if (TB) {
+        *(u16x8*)&Bs[q >> 2][8 * (q & 3)] = rb[j];
+      } else {
+        const int k = q / (T / 8), r = 8 * (q % (T / 8));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[r + e][k] = rb[j][e];
+      }
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();   // every wave is done with the previous chunk
+    stage();
     __syncthreads();
+    if (k0 + BK < K) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ++ks) {
       const int kk = ks * 16 + 8 * (lane >> 5);
-      const bf16x8 x = *(const bf16x8*)&As[wm * 32 + (lane & 31)][kk];
-      const bf16x8 y = *(const bf16x8*)&Bs[wn * 32 + (lane & 31)][kk];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
+      bf16x8 x[WB], y[WB];
+#pragma unroll
+      for (int i = 0; i < WB; ++i) x[i] = *(const bf16x8*)&As[wm * (T / 2) + 32 * i + (lane & 31)][kk];
+#pragma unroll
+      for (int j = 0; j < WB; ++j) y[j] = *(const bf16x8*)&Bs[wn * (T / 2) + 32 * j + (lane & 31)][kk];
+#pragma unroll
+      for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[i], y[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int m = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int n = n0 + wn * 32 + (lane & 31);
-    if (m < M && n < N) {
-      float z = acc[v];
-      if (epi & MLP_BIAS) z += bias[n];
-      if (epi & MLP_F32) Cf[(int64_t)m * ldc + n] = z;
-      if (epi & MLP_RELU_BF16) Cb[(int64_t)m * ldc + n] = (__bf16)fmaxf(z, 0.f);
-      else if (epi & MLP_BF16) Cb[(int64_t)m * ldc + n] = (__bf16)z;
-    }
-  }
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm * (T / 2) + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int n = n0 + wn * (T / 2) + 32 * j + (lane & 31);
+        if (m < M && n < N) {
+          float z = acc[i][j][v];
+          if (epi & MLP_BIAS) z += bias[n];
+          if (epi & MLP_F32) Cf[(int64_t)m * ldc + n] = z;
+          if (epi & MLP_RELU_BF16) Cb[(int64_t)m * ldc + n] = (__bf16)fmaxf(z, 0.f);
+          else if (epi & MLP_BF16) Cb[(int64_t)m * ldc + n] = (__bf16)z;
+        }
+      }
 }
 
 __global__ void k_f32_to_bf16(int64_t n, const float* __restrict__ x, __bf16* __restrict__ y) {
@@ -192,14 +276,41 @@ __global__ void k_target(int64_t m, int64_t mc, int t2, const double* __restrict
 // ------------------------------------------------------------ launchers
 static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
+// widest load along an operand's contiguous dimension that every segment
+// start allows: 16 bytes (leading dimension a multiple of 8 elements, base
+// 16-byte aligned), 4 bytes, or single elements
+static int seg_width(const void* p, int ld) {
+  const uintptr_t a = (uintptr_t)p;
+  if (ld % 8 == 0 && a % 16 == 0) return 8;
+  if (ld % 2 == 0 && a % 4 == 0) return 2;
+  return 1;
+}
+
+template <bool TA, bool TB>
+static void mlp_gemm_t(int M, int N, int K, const __bf16* A, int lda, const __bf16* B, int ldb, const float* bias,
+                       int epi, float* Cf, __bf16* Cb, int ldc, hipStream_t s) {
+  const int va = seg_width(A, lda), vb = seg_width(B, ldb);
+  // 128 x 128 tiles where they still give every CU at least two
+  // workgroups, else 64 x 64
+  const int64_t big = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  if (big >= 512) {
+    const dim3 g((M + 127) / 128, (N + 127) / 128);
+    hipLaunchKernelGGL((k_mlp_gemm<TA, TB, 128>), g, dim3(256), 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc,
+                       va, vb);
+  } else {
+    const dim3 g((M + 63) / 64, (N + 63) / 64);
+    hipLaunchKernelGGL((k_mlp_gemm<TA, TB, 64>), g, dim3(256), 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc,
+                       va, vb);
+  }
+}
+
 void mlp_gemm(bool ta, bool tb, int M, int N, int K, const __bf16* A, int lda, const __bf16* B, int ldb,
               const float* bias, int epi, float* Cf, __bf16* Cb, int ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  const dim3 g((M + 63) / 64, (N + 63) / 64), b(256);
-  if (!ta && !tb) hipLaunchKernelGGL((k_mlp_gemm<false, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc);
-  else if (ta && !tb) hipLaunchKernelGGL((k_mlp_gemm<true, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc);
-  else if (!ta && tb) hipLaunchKernelGGL((k_mlp_gemm<false, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc);
-  else hipLaunchKernelGGL((k_mlp_gemm<true, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc);
+  if (!ta && !tb) mlp_gemm_t<false, false>(M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc, s);
+  else if (ta && !tb) mlp_gemm_t<true, false>(M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc, s);
+  else if (!ta && tb) mlp_gemm_t<false, true>(M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc, s);
+  else mlp_gemm_t<true, true>(M, N, K, A, lda, B, ldb, bias, epi, Cf, Cb, ldc, s);
 }
 void mlp_to_bf16(int64_t n, const float* x, __bf16* y, hipStream_t s) {
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(n)), dim3(256), 0, s, n, x, y);

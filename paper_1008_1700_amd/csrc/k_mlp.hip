@@ -187,13 +187,26 @@ __global__ void k_relu_bwd(int64_t n, const float* __restrict__ dA, const float*
     dZ[i] = (__bf16)(Z[i] > 0.f ? dA[i] : 0.f);
 }
 
-// db[c] = sum over rows of dZ[r][c] (bf16 input, FP32 sum in row order)
-__global__ void k_bias_grad(int rows, int cols, const __bf16* __restrict__ dZ, float* __restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// db[c] = sum over rows of dZ[r][c] (bf16 input, FP32 sums).  A workgroup
+// takes 64 columns (one wave reads 64 consecutive entries of a row); its 16
+// row groups g sum rows g, g + 16, ... in order, and the 16 partial sums are
+// added pairwise in a fixed tree, so the result does not depend on timing.
+constexpr int kBiasGroups = 16;
+__global__ __launch_bounds__(64 * kBiasGroups) void k_bias_grad(int rows, int cols, const __bf16* __restrict__ dZ,
+                                                                float* __restrict__ db) {
+  __shared__ float part[kBiasGroups][64];
+  const int lc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lc;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += (float)dZ[(int64_t)r * cols + c];
-  db[c] = s;
+  if (c < cols)
+    for (int r = g; r < rows; r += kBiasGroups) s += (float)dZ[(int64_t)r * cols + c];
+  part[g][lc] = s;
+  __syncthreads();
+  for (int h = kBiasGroups / 2; h > 0; h >>= 1) {
+    if (g < h) part[g][lc] += part[g + h][lc];
+    __syncthreads();
+  }
+  if (g == 0 && c < cols) db[c] = part[0][lc];
 }
 
 // Adam (Kingma & Ba 2015, Algorithm 1) on FP32 master parameters; the bf16
@@ -324,7 +337,7 @@ void mlp_relu_bwd(int64_t n, const float* dA, const float* Z, __bf16* dZ, hipStr
   hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(n)), dim3(256), 0, s, n, dA, Z, dZ);
 }
 void mlp_bias_grad(int rows, int cols, const __bf16* dZ, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(k_bias_grad, dim3((cols + 255) / 256), dim3(256), 0, s, rows, cols, dZ, db);
+  hipLaunchKernelGGL(k_bias_grad, dim3((cols + 63) / 64), dim3(64 * kBiasGroups), 0, s, rows, cols, dZ, db);
 }
 void mlp_adam(int64_t n, float lr, float b1, float b2, float eps, int t, float* p, const float* g, float* m,
               float* v, __bf16* pb, hipStream_t s) {

@@ -209,3 +209,38 @@ def test_ilu_single_block():
         assert relerr(host(x), O.direct_solve(A.scipy(), f)) <= 1e-8
     finally:
         S.close()
+
+
+def test_ilu_many_right_hand_sides(c1, c1_oracle):
+    """Eight right-hand-side columns (the allocation the many-RHS workloads
+    use): the block solve of 5 columns (3 columns unused) against the
+    oracle, and a solve of 8 columns against the direct solution."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    A = c1["A"]
+    print("ILU(0) C1 8 columns", flush=True)
+    S = make_solver(c1, inner_tol=1e-10, max_rhs=8, retrieval=1, block_factor="ilu0", outer="bicgstab",
+                    inner_prec=1)
+    try:
+        S.factor()
+        y = np.random.default_rng(25).standard_normal((5, A.n))
+        g = torch.empty(5 * A.n, dtype=torch.float64, device="cuda")
+        ddps.ddps_block_solve(S.h, 5, dev_vec(y.ravel()), g)
+        got = host(g).reshape(5, -1)
+        for j in range(5):
+            exp = np.concatenate([O.solve_with(f, y[j, b.lo:b.hi])
+                                  for f, b in zip(c1_oracle.factors, c1_oracle.blocks)])
+            assert relerr(got[j], exp) <= 1e-12
+        xs = np.random.default_rng(26).uniform(-1, 1, (8, A.n))
+        F = np.stack([A.scipy() @ xs[j] for j in range(8)])
+        X = torch.zeros(8, A.n, dtype=torch.float64, device="cuda")
+        # kappa_inf(C1) is about 7e2, so a residual of 1e-10 bounds the error
+        # only by ~7e-8: the 1e-8 bar needs the residual at 1e-12
+        rc, info = ddps.ddps_solve_many(S.h, dev_vec(F), X, 1e-12, check=False)
+        print(f"  GPU {info.as_dict()}", flush=True)
+        assert rc == 0 and info.relres_inf <= 1e-12
+        for j in range(8):
+            assert relerr(host(X)[j], xs[j]) <= 1e-8
+    finally:
+        S.close()

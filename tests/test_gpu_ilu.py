@@ -244,3 +244,23 @@ def test_ilu_many_right_hand_sides(c1, c1_oracle):
             assert relerr(host(X)[j], xs[j]) <= 1e-8
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("slots", [1, 3])
+def test_ilu_spike_batches(c1, c1_oracle, slots):
+    """Spikes computed in several batches (a workspace of 1 or 3 blocks for
+    p = 4, as when memory holds fewer blocks than p): the reduced matrix built
+    from their tips is the oracle's."""
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    print(f"ILU(0) C1 work_slots {slots}", flush=True)
+    S = make_solver(c1, retrieval=1, block_factor="ilu0", work_slots=slots)
+    try:
+        S.factor()
+        m, _, _ = ddps.ddps_reduced_layout(S.h)
+        x = np.random.default_rng(27).standard_normal(m)
+        v = torch.empty(m, dtype=torch.float64, device="cuda")
+        ddps.ddps_reduced_matvec(S.h, 1, dev_vec(x), v)
+        assert relerr(host(v), c1_oracle.ghat_matvec(x)) <= 1e-12
+    finally:
+        S.close()

@@ -552,8 +552,8 @@ def run_c4(args):
         "eval_steps": len(ev),
         "solve_ms_prev": mean("prev_ms", ev), "solve_ms_learned": mean("learn_ms", ev),
         "inner_iters_prev": mean("prev_inner", ev), "inner_iters_learned": mean("learn_inner", ev),
-        "judge_resid_prev_median": float(np.median([r["r_prev"] for r in ev])) if ev else None,
-        "judge_resid_learned_median": float(np.median([r["r_learn"] for r in ev])) if ev else None,
+        "selection_resid_prev_median": float(np.median([r["r_prev"] for r in ev])) if ev else None,
+        "selection_resid_learned_median": float(np.median([r["r_learn"] for r in ev])) if ev else None,
         "learned_chosen": sum(bool(r["learned"]) for r in ev),
         "guess_ms": mean("guess_ms", ev), "features_ms": mean("features_ms", recs),
         "factor_ms": mean("factor_ms", recs), "train_s": out["train_s"],
@@ -631,7 +631,7 @@ def main():
     args.inner_tol = it_mix if args.inner_tol is None else args.inner_tol
     args.inner_tol_f64 = it_f64 if args.inner_tol_f64 is None else args.inner_tol_f64
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+        print("bench.py measures one GPU: this library has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
     import torch

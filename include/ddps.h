@@ -348,7 +348,7 @@ int ddps_reduced_rhs(ddps_handle h, int32_t k, const double* y, double* ghat);
  * side f is the restriction of the solution of Ax = f. */
 int ddps_reduced_restrict(ddps_handle h, int32_t k, const double* x, double* z);
 
-/* Judge of a candidate guess: res (host, double[k]) receives
+/* Selection residual of a candidate guess: res (host, double[k]) receives
  * ||ghat - G^ z||_2 over the index set c for each column (z is masked to c
  * first); if rvec (device, double[m*k]) is not NULL it receives the residual
  * vector itself, zero off c.  Uses the handle's reduced work vectors, so the

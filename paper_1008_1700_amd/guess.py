@@ -7,7 +7,7 @@ plain solves run, trains the per-interface network on the GPU, and at later
 steps proposes z^_0 = z^prev + s_j net([r_j / s_j, z^prev_j / q_j, cos, sin])
 from the reduced residual r = g^ - G^ z^prev of the fallback guess
 (s_j = max |r_j|, q_j = max |z^prev_j|), keeping whichever of the two
-candidates has the smaller reduced residual ||g^ - G^ z^_0||_2 (the judge).
+candidates has the smaller reduced residual ||g^ - G^ z^_0||_2 (the selection rule).
 
 Orchestration only: every numerical step runs in libddps.so
 (ddps_reduced_rhs, ddps_guess_*, ddps_mlp_*, ddps_reduced_residual,

@@ -190,7 +190,7 @@ def test_reduced_rhs_restrict_and_residual(c1_setup):
     z = torch.empty(m, dtype=torch.float64, device="cuda")
     ddps.ddps_reduced_restrict(S.h, 1, dev_vec(x), z)
     assert np.array_equal(host(z), x[cand] * mask)
-    # judge: ||g^ - G^ z||_2 on c
+    # selection residual: ||g^ - G^ z||_2 on c
     zc = x[P.c]
     r_ref = np.linalg.norm(rec["ghat"] - P.ghat_matvec(zc))
     r = ddps.ddps_reduced_residual(S.h, 1, gh, z)[0]
@@ -272,7 +272,7 @@ def test_guess_seeds_the_reduced_solve(c1_setup):
 
 
 # ------------------------------------------------------------ gain
-def test_learned_guess_judge_on_time_sequence():
+def test_learned_guess_selection_on_time_sequence():
     """Implicit-Euler convection-diffusion (128 x 128, |v| = 50 rotating 1.2
     degrees per step, dt = 1e-3, p = 8): 60 plain steps train the network,
     the next 20 solve each step twice, once from the previous-step guess and
@@ -280,7 +280,7 @@ def test_learned_guess_judge_on_time_sequence():
 
     What is asserted: the network learns (loss falls fivefold), its guess
     starts the reduced solve from a smaller reduced residual than the
-    previous step's solution, the judge takes whichever start has the
+    previous step's solution, the selection takes whichever start has the
     smaller residual, and every solve converges.  What is not asserted is an
     iteration gain: there is none.  The reduced BiCGStab gains about a
     decade per iteration, so a start residual a few times smaller is worth a
@@ -310,7 +310,7 @@ def test_learned_guess_judge_on_time_sequence():
     rl = np.array([r["r_learn"] for r in ev])
     ip = sum(r["prev_inner"] for r in ev)
     il = sum(r["learn_inner"] for r in ev)
-    print(f"judge residual prev/learned (median) {np.median(rp):.3e} / {np.median(rl):.3e}; "
+    print(f"selection residual prev/learned (median) {np.median(rp):.3e} / {np.median(rl):.3e}; "
           f"learned chosen {sum(r['learned'] for r in ev)}/20; inner iterations prev {ip} learned {il}")
     assert np.median(rl) < 0.5 * np.median(rp)
     assert all(r["learned"] == (r["r_learn"] < r["r_prev"]) for r in ev)
@@ -357,7 +357,7 @@ def test_learned_guess_in_every_application(retrieval):
 
 def test_untrained_network_is_retired_by_the_trial():
     """An untrained network attached to the handle: the first reduced solves
-    alternate between leaving it out and letting the judge consider it, and
+    alternate between leaving it out and letting the selection consider it, and
     after 8 solves per arm it is retired unless its solves took at least
     half an iteration fewer.  An untrained network cannot do that; afterwards
     no candidates are tried, and every solve still matches the direct one."""

@@ -264,3 +264,55 @@ def test_ilu_spike_batches(c1, c1_oracle, slots):
         assert relerr(host(v), c1_oracle.ghat_matvec(x)) <= 1e-12
     finally:
         S.close()
+
+
+def test_ilu_c5_sampled():
+    """The benchmark workload at full size (3D 40x40x4096, p = 512, FP32
+    tips): for sampled blocks, the block solve against the oracle's ILU(0)
+    of that block (1e-12), and sampled spike columns, read back as columns
+    of G^ = I + G(c, c), against the oracle's spike column at every reduced
+    row of the block, element by element (the spikes are computed and kept
+    in FP32: 1e-5 of the column's largest entry)."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    d = configs.c5()
+    A, part = d["A"], d["part_ptr"]
+    S_ = A.scipy().tocsc()
+    print("ILU(0) C5 setup", flush=True)
+    S = ddps.Solver(A, part, dtype="f32", retrieval=1, block_factor="ilu0")
+    try:
+        S.factor()
+        m, t, _ = ddps.ddps_reduced_layout(S.h)
+        c = torch.empty(m, dtype=torch.int64, device="cuda")
+        mask = torch.empty(m, dtype=torch.float64, device="cuda")
+        ddps.ddps_reduced_layout(S.h, c, mask)
+        ch = host(c)
+        y = np.random.default_rng(28).standard_normal(A.n)
+        g = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        ddps.ddps_block_solve(S.h, 1, dev_vec(y), g)
+        gh = host(g)
+        e = torch.zeros(m, dtype=torch.float64, device="cuda")
+        v = torch.empty(m, dtype=torch.float64, device="cuda")
+        for blk in (1, 300, 511):
+            lo, hi = int(part[blk]), int(part[blk + 1])
+            fac = O.factor_block_ilu0(S_[lo:hi, lo:hi].tocsr())
+            assert relerr(gh[lo:hi], O.ilu0_solve(fac, y[lo:hi])) <= 1e-12, blk
+            rows = np.nonzero((ch >= lo) & (ch < hi))[0]        # reduced rows of this block
+            for q in (0, 777, t - 1):
+                col = lo - t + q                                  # left coupling column q
+                j = int(np.nonzero(ch == col)[0][0])
+                e.zero_()
+                e[j] = 1.0
+                ddps.ddps_reduced_matvec(S.h, 1, e, v)
+                got = host(v)
+                got[j] -= 1.0
+                rcol = S_[lo:hi, col].toarray().ravel()
+                exp = O.ilu0_solve(fac, rcol)
+                ref = np.max(np.abs(exp))
+                assert np.max(np.abs(got[rows] - exp[ch[rows] - lo])) <= 1e-5 * ref, (blk, q)
+                others = np.setdiff1d(np.arange(m), rows)
+                assert np.max(np.abs(got[others])) == 0.0, (blk, q)
+        print("  sampled blocks and spike columns match", flush=True)
+    finally:
+        S.close()

@@ -215,8 +215,11 @@ int ddps_set_guess(ddps_handle h, const double* zhat0, int32_t k);
  * columns m = 2 t (p - 1) (host).  If c is not NULL it receives (device,
  * int64[m]) the global column index of each candidate, ascending; if mask is
  * not NULL it receives (device, double[m]) 1 for candidates in the index set
- * c of stage 5 and 0 for dropped or structurally zero columns.  t and b
- * (host, may be NULL) receive the tile size and half-bandwidth. */
+ * c of stage 5 and 0 for dropped or structurally zero columns; the dropping
+ * rule is applied by ddps_factor, so asking for the mask before a successful
+ * factorisation (or after ddps_refactor_values, before the next one) returns
+ * DDPS_E_STATE.  t and b (host, may be NULL) receive the tile size and
+ * half-bandwidth. */
 int ddps_reduced_layout(ddps_handle h, int64_t* m, int64_t* c, double* mask, int32_t* t, int32_t* b);
 
 /* Reduced vectors of the last preconditioner application of the last solve

@@ -2506,6 +2506,7 @@ int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t
 
 int ddps_reduced_layout(ddps_handle h, int64_t* m, int64_t* c, double* mask, int32_t* t, int32_t* b) {
   if (!h) return DDPS_E_ARG;
+  if (mask && h->m && !h->factored) return DDPS_E_STATE;   // the dropping rule runs in ddps_factor
   if (m) *m = h->m;
   if (t) *t = h->t;
   if (b) *b = h->b;

@@ -177,6 +177,10 @@ def test_ilu_option_errors(c1):
         ddps.Solver(B, c1["part_ptr"], retrieval=1, block_factor="ilu0")
     G = make_solver(c1, retrieval=1, block_factor="ilu0")
     try:
+        # the kept-column mask exists once a factorisation has applied the dropping rule
+        m, _, _ = ddps.ddps_reduced_layout(G.h)
+        with pytest.raises(ddps.DDPSError):
+            ddps.ddps_reduced_layout(G.h, None, torch.empty(m, dtype=torch.float64, device="cuda"))
         G.factor()
         buf = torch.empty(64 * 64, dtype=torch.float64, device="cuda")
         with pytest.raises(ddps.DDPSError):

@@ -252,14 +252,15 @@ def random_banded(n, b, seed, density=0.6, margin=0.5, nonsym=True):
     return CSR(n, A.row_ptr, A.col, val)
 
 
-def random_geometric(n, degree, seed, shuffle=True):
+def random_geometric(n, degree, seed, shuffle=True, sigma=None, margin=0.5, margin_rand=1.0):
     """A general (non-banded) sparse system: n points uniform in the unit
     square, each joined to the points within the radius that gives about
     `degree` neighbours on average; off-diagonal entries -(0.5 + u) with u ~
-    U[0,1) independently for a_ij and a_ji (nonsymmetric), diagonal = the
-    larger of the absolute row and column sums + 0.5 + U[0,1): a strictly
-    row- and column-diagonally-dominant M-matrix.  The rows come in a random
-    order (shuffle) or sorted by x, then y."""
+    U[0,1) (or, with sigma, -exp(sigma z) with z ~ N(0,1)) independently for
+    a_ij and a_ji (nonsymmetric), diagonal = the larger of the absolute row
+    and column sums + margin + margin_rand U[0,1): a strictly row- and
+    column-diagonally-dominant M-matrix.  The rows come in a random order
+    (shuffle) or sorted by x, then y."""
     from scipy.spatial import cKDTree
     rng = np.random.default_rng(seed)
     pts = rng.random((n, 2))
@@ -269,11 +270,11 @@ def random_geometric(n, degree, seed, shuffle=True):
     pairs = cKDTree(pts).query_pairs(radius, output_type="ndarray")
     i = np.concatenate([pairs[:, 0], pairs[:, 1]])
     j = np.concatenate([pairs[:, 1], pairs[:, 0]])
-    v = -(0.5 + rng.random(len(i)))
+    v = -(0.5 + rng.random(len(i))) if sigma is None else -np.exp(sigma * rng.standard_normal(len(i)))
     import scipy.sparse as sp
     M = sp.csr_matrix((v, (i, j)), shape=(n, n))
     rs = np.asarray(abs(M).sum(axis=1)).ravel()
     cs = np.asarray(abs(M).sum(axis=0)).ravel()
-    M = (M + sp.diags(np.maximum(rs, cs) + 0.5 + rng.random(n))).tocsr()
+    M = (M + sp.diags(np.maximum(rs, cs) + margin + margin_rand * rng.random(n))).tocsr()
     M.sort_indices()
     return CSR(n, M.indptr, M.indices, M.data)

@@ -100,6 +100,11 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_spikes(const IluBlock* __re
   const int64_t n = B.n;
   const int64_t r0 = left ? 0 : n - t;   // rows above r0 stay zero in the forward solve
   const int j = left ? c : c - t;
+  // the row just finished (r - 1 down the block, r + 1 up it) is taken from
+  // a register, as stored (rounded to T), instead of being loaded back right
+  // after its store; the row index is the same in every lane, so the choice
+  // does not diverge
+  double prev = 0.0;
   for (int64_t r = r0; r < n; ++r) {
     const int64_t R = B.s + r;
     double acc;
@@ -111,16 +116,24 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_spikes(const IluBlock* __re
     const int64_t qe = dg[R];
     for (int64_t q = lo[R]; q < qe; ++q) {
       const int64_t k = col[q] - B.s;
-      if (k >= r0) acc -= fv[q] * (double)W[k * t2 + c];
+      if (k >= r0) acc -= fv[q] * (k == r - 1 ? prev : (double)W[k * t2 + c]);
     }
-    W[r * t2 + c] = (T)acc;
+    const T y = (T)acc;
+    W[r * t2 + c] = y;
+    prev = (double)y;
   }
+  double next = 0.0;
   for (int64_t r = n - 1; r >= 0; --r) {
     const int64_t R = B.s + r;
     const int64_t d = dg[R];
     double acc = r >= r0 ? (double)W[r * t2 + c] : 0.0;
-    for (int64_t q = d + 1; q < hi[R]; ++q) acc -= fv[q] * (double)W[(col[q] - B.s) * t2 + c];
-    W[r * t2 + c] = (T)(acc / fv[d]);
+    for (int64_t q = d + 1; q < hi[R]; ++q) {
+      const int64_t k = col[q] - B.s;
+      acc -= fv[q] * (k == r + 1 ? next : (double)W[k * t2 + c]);
+    }
+    const T x = (T)(acc / fv[d]);
+    W[r * t2 + c] = x;
+    next = (double)x;
   }
 }
 

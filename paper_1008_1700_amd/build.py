@@ -24,7 +24,7 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    "-Wno-unused-command-line-argument",
+    "-Wall", "-Wextra", "-Wno-unused-command-line-argument",
 ]
 
 

@@ -311,13 +311,13 @@ struct ddps_ctx {
     a = nullptr;
     if (!tim_on[kind] || capturing) return;
     a = get_event();
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
   }
   void tim_begin(int kind, hipEvent_t& a) { tim_begin(kind, a, stream); }
   void tim_end(int kind, hipEvent_t a, double flops, double bytes_, hipStream_t s) {
     if (!a) return;
     hipEvent_t b2 = get_event();
-    hipEventRecord(b2, s);
+    (void)hipEventRecord(b2, s);
     tim[kind].push_back({a, b2, flops, bytes_});
   }
   void tim_end(int kind, hipEvent_t a, double flops, double bytes_) { tim_end(kind, a, flops, bytes_, stream); }
@@ -328,18 +328,18 @@ struct ddps_ctx {
         allocs.erase(allocs.begin() + i);
         break;
       }
-    hipFree(q);
+    (void)hipFree(q);
   }
   void drop_graph() {
-    if (graph_exec) hipGraphExecDestroy(graph_exec);
-    if (graph) hipGraphDestroy(graph);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     graph_exec = nullptr;
     graph = nullptr;
     drop_capture_events();
   }
   void drop_capture_events() {
-    if (cap_fork) hipEventDestroy(cap_fork);
-    for (auto e : cap_gevent) hipEventDestroy(e);
+    if (cap_fork) (void)hipEventDestroy(cap_fork);
+    for (auto e : cap_gevent) (void)hipEventDestroy(e);
     cap_fork = nullptr;
     cap_gevent.clear();
   }
@@ -350,7 +350,7 @@ struct ddps_ctx {
       return e;
     }
     hipEvent_t e;
-    hipEventCreate(&e);
+    (void)hipEventCreate(&e);
     return e;
   }
 };
@@ -1678,31 +1678,32 @@ const char* ddps_status_string(int s) {
 
 void ddps_destroy(ddps_handle h) {
   if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (int k = 0; k < TK_N; ++k)
     for (auto& r : h->tim[k]) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
-  for (auto e : h->ev_pool) hipEventDestroy(e);
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   h->drop_graph();
-  if (h->fstream) hipStreamSynchronize(h->fstream);
+  if (h->fstream) (void)hipStreamSynchronize(h->fstream);
   for (auto gs : h->gstream) {
-    hipStreamSynchronize(gs);
-    hipStreamDestroy(gs);
+    (void)hipStreamSynchronize(gs);
+    (void)hipStreamDestroy(gs);
   }
-  for (auto ge : h->gevent) hipEventDestroy(ge);
-  if (h->fstream) hipStreamDestroy(h->fstream);
-  if (h->fork_ev) hipEventDestroy(h->fork_ev);
-  if (h->join_ev) hipEventDestroy(h->join_ev);
-  if (h->ev0) hipEventDestroy(h->ev0);
-  if (h->ev1) hipEventDestroy(h->ev1);
-  for (void* q : h->allocs) hipFree(q);
-  if (h->h_state) hipHostFree(h->h_state);
-  if (h->h_out) hipHostFree(h->h_out);
+  for (auto ge : h->gevent) (void)hipEventDestroy(ge);
+  if (h->fstream) (void)hipStreamDestroy(h->fstream);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (void* q : h->allocs) (void)hipFree(q);
+  if (h->h_state) (void)hipHostFree(h->h_state);
+  if (h->h_out) (void)hipHostFree(h->h_out);
   delete h;
 }
 
+extern "C++" {  // internal helpers: C++ linkage
 namespace {
 
 // Host plan of the incomplete-factor form: per row the CSR positions of its
@@ -1840,6 +1841,7 @@ int ilu_upload(ddps_ctx* h, const IluPlan& P) {
 }
 
 }  // namespace
+}  // extern "C++"
 
 int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, const int64_t* row_ptr,
                const int32_t* col, const double* val, int64_t nnz, const ddps_options* opt) {
@@ -1886,7 +1888,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) return fail(DDPS_E_HIP);
   if (hipHostMalloc((void**)&h->h_state, sizeof(KState)) != hipSuccess) return fail(DDPS_E_HIP);
   if (hipHostMalloc((void**)&h->h_out, sizeof(double) * 4 * kMaxRhs) != hipSuccess) return fail(DDPS_E_HIP);
-  hipEventRecord(h->ev0, h->stream);
+  (void)hipEventRecord(h->ev0, h->stream);
 
   // copy the CSR and scan it
   int rc;
@@ -2119,10 +2121,10 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
     return fail(DDPS_E_HIP);
   h->use_graph = o.factor_graph != 0;
   if ((rc = build_schedules(h))) return fail(rc);
-  hipEventRecord(h->ev1, s);
+  (void)hipEventRecord(h->ev1, s);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(DDPS_E_HIP);
   float ms = 0;
-  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
   h->t_setup_ms = ms;
   *out = h;
   return DDPS_OK;
@@ -2130,7 +2132,7 @@ int ddps_setup(ddps_handle* out, int64_t n, int32_t p, const int64_t* part_ptr, 
 
 int ddps_factor(ddps_handle h) {
   if (!h) return DDPS_E_ARG;
-  hipEventRecord(h->ev0, h->stream);
+  (void)hipEventRecord(h->ev0, h->stream);
   // the factorisation runs on the internal stream, ordered after the
   // caller's stream and joined back into it
   HIPCHK(hipEventRecord(h->fork_ev, h->stream));
@@ -2151,7 +2153,7 @@ int ddps_factor(ddps_handle h) {
       hipError_t e2 = hipStreamEndCapture(h->fstream, &g);
       h->capturing = false;
       if (rc || e2 != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         last_hip_error() = e2;
         return rc ? rc : DDPS_E_HIP;
       }
@@ -2165,14 +2167,14 @@ int ddps_factor(ddps_handle h) {
   }
   HIPCHK(hipEventRecord(h->join_ev, h->fstream));
   HIPCHK(hipStreamWaitEvent(h->stream, h->join_ev, 0));
-  hipEventRecord(h->ev1, h->stream);
+  (void)hipEventRecord(h->ev1, h->stream);
   unsigned long long bad = 0;
   unsigned int flags = 0;
   HIPCHK(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(&flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   float ms = 0;
-  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
   h->t_factor_ms = ms;
   if (flags) return DDPS_E_ARG;
   if (bad != ~0ull) {
@@ -2210,7 +2212,7 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   hipStream_t s = h->stream;
   const int R = h->R;
   const int64_t n = h->n;
-  hipEventRecord(h->ev0, s);
+  (void)hipEventRecord(h->ev0, s);
   // internal copies with leading dimension n; unused columns are zero
   HIPCHK(hipMemcpy2DAsync(h->d_fo, n * 8, F, ldf * 8, n * 8, k, hipMemcpyDeviceToDevice, s));
   if (h->opt.use_x0)
@@ -2392,10 +2394,10 @@ static int solve_impl(ddps_handle h, int k, const double* F, int64_t ldf, double
   // true residual of the final iterate
   if ((rc = resid(h, h->d_xo, h->d_ro, rinf, r2, finf, f2))) return rc;
   HIPCHK(hipMemcpy2DAsync(X, ldx * 8, h->d_xo, n * 8, n * 8, k, hipMemcpyDeviceToDevice, s));
-  hipEventRecord(h->ev1, s);
+  (void)hipEventRecord(h->ev1, s);
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0;
-  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
   h->t_solve_ms = ms;
   h->last_k = k;
   double worst_inf = 0, worst_2 = 0;
@@ -2746,11 +2748,12 @@ int ddps_set_execution(ddps_handle h, int32_t streams, int32_t graph, int32_t ti
   return build_schedules(h);
 }
 
+extern "C++" {  // internal helpers: C++ linkage
 namespace {
 
 std::string tune_key(ddps_ctx* h) {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   std::string arch = "gpu";
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
@@ -2843,7 +2846,9 @@ void cache_store(const char* path, const std::string& key, int streams, int poli
 }
 
 }  // namespace
+}  // extern "C++"
 
+extern "C++" {  // internal helpers: C++ linkage
 namespace {
 // Durations (ms) of the factor GEMM launches of one ddps_factor, in order.
 int time_gemm_launches(ddps_ctx* h, std::vector<float>& out) {
@@ -2911,6 +2916,7 @@ int tune_launch_modes(ddps_ctx* h, int groups, double* ms) {
   return DDPS_OK;
 }
 }  // namespace
+}  // extern "C++"
 
 int ddps_autotune(ddps_handle h, const char* cache_path, double budget_s, int32_t* streams, int32_t* tile_policy,
                   double* factor_ms) {
@@ -3031,7 +3037,7 @@ int ddps_timing_read(ddps_handle h, int32_t kind, int64_t* launches, double* ms,
   double tot = 0, fl = 0, by = 0;
   for (auto& r : h->tim[kind]) {
     float e = 0;
-    hipEventElapsedTime(&e, r.a, r.b);
+    (void)hipEventElapsedTime(&e, r.a, r.b);
     tot += e;
     fl += r.flops;
     by += r.bytes;
@@ -3062,7 +3068,7 @@ int ddps_residual_norms(int64_t n, int32_t k, const int64_t* row_ptr, const int3
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(norms, out, sizeof(double) * 4 * k, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(buf);
+  (void)hipFree(buf);
   if (e != hipSuccess) {
     last_hip_error() = e;
     return DDPS_E_HIP;

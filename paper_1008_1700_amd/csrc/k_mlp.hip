@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_mse(int64_t n, float scale, const float
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -237,7 +237,7 @@ __device__ double block_absmax(const double* v, const double* mk, int t2, double
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int q = 128; q > 0; q >>= 1) {
-    if (threadIdx.x < q) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + q]);
+    if ((int)threadIdx.x < q) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + q]);
     __syncthreads();
   }
   const double r = red[0] > 1e-300 ? red[0] : 1.0;

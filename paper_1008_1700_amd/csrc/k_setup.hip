@@ -165,7 +165,7 @@ __global__ void k_scatter(int64_t n, int p, int t, const int64_t* __restrict__ p
 
 // Identity rows on top of short blocks (padding): diagonal of tile 0.
 template <typename T>
-__global__ void k_pad_identity(int p, int t, const BlockInfo* __restrict__ blocks, T* __restrict__ tiles) {
+__global__ void k_pad_identity(int /*p*/, int t, const BlockInfo* __restrict__ blocks, T* __restrict__ tiles) {
   const BlockInfo B = blocks[blockIdx.x];
   for (int64_t i = threadIdx.x; i < B.pad; i += blockDim.x)
     tiles[B.tiles + i * t + i] = T(1);
@@ -187,7 +187,7 @@ __global__ void k_mask(int p, int t, double delta, const BlockInfo* __restrict__
   red[threadIdx.x] = mu;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   mu = red[0];

@@ -252,7 +252,8 @@ __global__ __launch_bounds__(256) void k_bicg_xr(int it, int64_t m, double tol, 
                                                  const double* __restrict__ s2,
                                                  const double* __restrict__ s3,
                                                  KState* __restrict__ st, double* __restrict__ x,
-                                                 const double* __restrict__ p, const double* __restrict__ s,
+                                                 const double* __restrict__ /*p: the update uses px*/,
+                                                 const double* __restrict__ s,
                                                  const double* __restrict__ t, double* __restrict__ r,
                                                  const double* __restrict__ rt, double* __restrict__ part,
                                                  const double* __restrict__ px, const double* __restrict__ sx) {

@@ -217,9 +217,9 @@ int ddps_mlp_train_step(ddps_mlp M, int32_t batch, const float* X, const float* 
 
 void ddps_mlp_destroy(ddps_mlp M) {
   if (!M) return;
-  if (M->stream) hipStreamSynchronize(M->stream);
-  for (void* q : M->allocs) hipFree(q);
-  if (M->h_part) hipHostFree(M->h_part);
+  if (M->stream) (void)hipStreamSynchronize(M->stream);
+  for (void* q : M->allocs) (void)hipFree(q);
+  if (M->h_part) (void)hipHostFree(M->h_part);
   delete M;
 }
 

@@ -117,3 +117,66 @@ def test_random_geometric_system_becomes_banded():
     x = np.random.default_rng(1).standard_normal(A.n)
     Ap = sp.csr_matrix((gs.val, gs.col, gs.row_ptr), shape=(A.n, A.n))
     assert np.allclose(gs.from_perm(Ap @ gs.to_perm(x)), A.scipy() @ x, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ property tests
+from hypothesis import given, settings, strategies as st
+
+
+@st.composite
+def sparse_patterns(draw):
+    """Random square patterns (possibly nonsymmetric, with isolated rows and
+    several components), stored as sorted CSR with the diagonal."""
+    n = draw(st.integers(1, 60))
+    density = draw(st.floats(0.0, 0.3))
+    seed = draw(st.integers(0, 2**31 - 1))
+    rng = np.random.default_rng(seed)
+    M = sp.random(n, n, density=density, random_state=rng, format="csr")
+    M = (M + sp.eye(n)).tocsr()
+    M.sort_indices()
+    M.data = rng.uniform(-1.0, 1.0, M.nnz)
+    return M
+
+
+@settings(max_examples=60, deadline=None)
+@given(sparse_patterns())
+def test_rcm_properties(M):
+    """For any pattern: the ordering is a permutation; the permuted CSR is
+    S[perm][:, perm] entry for entry; the reported bandwidth is the permuted
+    matrix's; and every connected component of A + A^T occupies one
+    contiguous index range (breadth-first numbering component by
+    component)."""
+    from scipy.sparse.csgraph import connected_components
+    ddps = _lib()
+    n = M.shape[0]
+    perm = ddps.ddps_rcm(n, M.indptr, M.indices)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    rp, cl, vl = ddps.ddps_permute_csr(n, M.indptr, M.indices, M.data, perm)
+    P = sp.csr_matrix((vl, cl, rp), shape=(n, n))
+    E = M[perm][:, perm].tocsr()
+    E.sort_indices()
+    assert np.array_equal(P.indptr, E.indptr) and np.array_equal(P.indices, E.indices)
+    assert np.array_equal(P.data, E.data)
+    assert ddps.ddps_bandwidth(n, rp, cl) == _band(P)
+    _, lab = connected_components(M + M.T, directed=False)
+    lp = lab[perm]
+    for c in np.unique(lp):
+        idx = np.nonzero(lp == c)[0]
+        assert idx[-1] - idx[0] + 1 == idx.size
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 5000), st.integers(0, 600), st.integers(1, 64))
+def test_partition_properties(n, b, p_max):
+    """Equal slabs: they cover [0, n) in order, differ in size by at most
+    one, number at most p_max, and are at least 2t rows (t = b rounded up to
+    64, at least 64) whenever there is more than one."""
+    ddps = _lib()
+    part = ddps.ddps_partition_rows(n, b, p_max)
+    p = len(part) - 1
+    sizes = np.diff(part)
+    t = max(64, -(-b // 64) * 64)
+    assert part[0] == 0 and part[-1] == n and 1 <= p <= p_max
+    assert sizes.min() >= 1 and sizes.max() - sizes.min() <= 1
+    if p > 1:
+        assert sizes.min() >= 2 * t

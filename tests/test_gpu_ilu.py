@@ -320,3 +320,36 @@ def test_ilu_c5_sampled():
         print("  sampled blocks and spike columns match", flush=True)
     finally:
         S.close()
+
+
+def test_ilu_block_jacobi(c1):
+    """delta = 1 drops every coupling column (the dropping rule keeps only
+    columns above the largest norm): P = D~, block Jacobi with incomplete
+    blocks.  The reduced system is empty in effect (mask all zero, as the
+    oracle's c), and the outer BiCGStab reaches the direct solution (its
+    iteration count is printed beside the oracle's; iterate histories depend
+    on rounding order and are not compared)."""
+    from oracle import ddps_oracle as O
+    from paper_1008_1700_amd import ddps
+    torch = torch_cuda()
+    A = c1["A"]
+    print("ILU(0) C1 delta 1", flush=True)
+    S = make_solver(c1, delta=1.0, retrieval=1, block_factor="ilu0", outer="bicgstab", inner_tol=1e-10)
+    try:
+        S.factor()
+        m, _, _ = ddps.ddps_reduced_layout(S.h)
+        mask = torch.empty(m, dtype=torch.float64, device="cuda")
+        ddps.ddps_reduced_layout(S.h, None, mask)
+        assert float(host(mask).sum()) == 0.0
+        f = c1["f"]
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, info = S.solve(dev_vec(f), x, 1e-10, check=False)
+        xo, oinfo, P = O.solve(A.n, A.row_ptr, A.col, A.val, c1["part_ptr"], f, delta=1.0, tol=1e-10,
+                               outer="bicgstab", block_factor="ilu0")
+        print(f"  GPU outer {info.outer_iters}, oracle outer {oinfo.outer_iters}, oracle m {P.m}", flush=True)
+        assert P.m == 0
+        assert rc == 0 and info.relres_inf <= 1e-10
+        assert relerr(host(x), O.direct_solve(A.scipy(), f)) <= 1e-8
+        assert relerr(host(x), xo) <= 1e-8
+    finally:
+        S.close()

@@ -290,8 +290,9 @@ def run_delta_sweep(args):
     geometric graph of 400,000 points, about 8 neighbours, lognormal(0,1)
     coupling magnitudes, diagonal dominance margin 0.02-0.04) reordered by
     reverse Cuthill-McKee and cut into 16 equal slabs.  FP64 exact block
-    factors and ILU(0) block factors, both with the spike tips only.  F2
-    marks a run that ends above the tolerance, as in the paper."""
+    factors, bf16x3 exact block factors (FP32 storage) and FP64 ILU(0) block
+    factors, all with the spike tips only.  F2 marks a run that ends above
+    the tolerance, as in the paper."""
     import torch
     from paper_1008_1700_amd import ddps
     from workloads import pde
@@ -304,9 +305,9 @@ def run_delta_sweep(args):
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     tol = 1e-5
     rows = []
-    for form in ("lu", "ilu0"):
+    for form, dtype in (("lu", "f64"), ("lu", "bf16x3"), ("ilu0", "f64")):
         for dl in SWEEP_DELTAS:
-            S = ddps.Solver(gs, gs.part_ptr, dtype="f64", delta=dl, outer="bicgstab", inner_tol=1e-4,
+            S = ddps.Solver(gs, gs.part_ptr, dtype=dtype, delta=dl, outer="bicgstab", inner_tol=1e-4,
                             inner_maxit=100, outer_maxit=1000, retrieval=1, block_factor=form)
             S.factor()
             S.factor()
@@ -318,17 +319,17 @@ def run_delta_sweep(args):
                 ddps.ddps_reduced_layout(S.h, cidx, mask)
             x.zero_()
             rc, info = S.solve(f, x, tol, check=False)
-            r = dict(block_factor=form, delta=dl, kept_columns=int(mask[:m].sum().item()) if m else 0,
+            r = dict(block_factor=form, dtype=dtype, delta=dl, kept_columns=int(mask[:m].sum().item()) if m else 0,
                      outer_iters=info.outer_iters, applications=info.applications,
                      inner_iters_avg=info.inner_iters_avg, relres_inf=info.relres_inf,
                      status="ok" if info.relres_inf <= tol else "F2", factor_ms=info.t_factor_ms,
                      solve_ms=info.t_solve_ms, rc=rc)
-            log(f"delta sweep {form} delta={dl:g}: {json.dumps(r)}")
+            log(f"delta sweep {form} {dtype} delta={dl:g}: {json.dumps(r)}")
             rows.append(r)
             S.close()
     torch.cuda.empty_cache()
     print(json.dumps(dict(metric="DDPS outer BiCGStab iterations against the drop tolerance (Table 6 setting)",
-                          unit="outer iterations", higher_is_better=False, n_gpus=1, dtype="f64",
+                          unit="outer iterations", higher_is_better=False, n_gpus=1, dtype="f64, bf16x3+f64",
                           data="synthetic",
                           config={"workload": "random geometric graph, n=400000, ~8 neighbours, lognormal(0,1) "
                                               "couplings, RCM + 16 equal slabs", "n": A.n, "nnz": A.nnz,

@@ -477,7 +477,8 @@ int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t
  * sparse matrices.  The paper partitions general sparse matrices after a
  * fill-reducing / bandwidth-reducing reordering (Section 3; it uses METIS);
  * this path needs banded blocks, so a general matrix is first reordered by
- * reverse Cuthill-McKee (Cuthill & McKee 1969; George & Liu 1981), which
+ * reverse Cuthill-McKee (Cuthill & McKee 1969, reversed, started from a
+ * pseudo-peripheral node after George & Liu 1979), which
  * makes the profile of A + A^T narrow, and then cut into equal row slabs.
  * All arrays here are host arrays; nothing touches the GPU. */
 
@@ -490,19 +491,22 @@ int ddps_guess_trial(ddps_handle h, int64_t* solves, double* mean_iters, int32_t
  * (n < 0, null pointers for n > 0, a column outside [0, n)). */
 int ddps_rcm(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t* perm);
 
-/* Half-bandwidth b = max |i - j| over the stored entries (int64, written). */
+/* Half-bandwidth b = max |i - j| over the stored entries (int64, written).
+ * Errors: DDPS_E_ARG (n < 0, null pointers, a column outside [0, n)). */
 int ddps_bandwidth(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t* b);
 
 /* B = P A P^T for perm from ddps_rcm (new row i = old row perm[i]):
  * out_row_ptr[n+1], out_col[nnz], out_val[nnz] written, columns sorted
- * ascending within each row.  val / out_val may be null (pattern only). */
+ * ascending within each row.  val / out_val may be null (pattern only).
+ * Errors: DDPS_E_ARG (perm not a permutation of [0, n), a column outside
+ * [0, n), null pointers). */
 int ddps_permute_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                      const int64_t* perm, int64_t* out_row_ptr, int32_t* out_col, double* out_val);
 
 /* Row partition of a matrix with half-bandwidth b into at most p_max equal
  * slabs (sizes differing by at most one row) such that every slab has at
- * least 2t rows, t = b rounded up to a multiple of 64 (what ddps_setup
- * requires).  part_ptr (int64[p_max + 1]) and *p (the slabs used, >= 1) are
+ * least 2t rows, t = b rounded up to a multiple of 64 and at least 64
+ * (what ddps_setup requires); one slab when n < 4t.  part_ptr (int64[p_max + 1]) and *p (the slabs used, >= 1) are
  * written.  Errors: DDPS_E_ARG (p_max < 1, n < 1, b < 0). */
 int ddps_partition_rows(int64_t n, int64_t b, int32_t p_max, int64_t* part_ptr, int32_t* p);
 
